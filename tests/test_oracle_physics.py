@@ -1,0 +1,148 @@
+"""Physics pins of the oracle: sigma-form brute force, loss closed forms, equilibrium, BKW."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+import fks_inputs
+from oracle import bkw, make_plan, sigma_form
+from oracle.collide import collide_fast, loss_field
+from oracle.conserve import moments
+from oracle.tables import VHS
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_sigma_form_golden_is_reproducible():
+    with open(os.path.join(GOLDEN, "sigma_form_hard_spheres.json")) as fh:
+        gold = json.load(fh)
+    fun = sigma_form.mixture([(c[0], tuple(c[1]), c[2]) for c in gold["components"]])
+    p = gold["points"][1]
+    q = sigma_form.collision_integral(fun, np.array(p["v"]), 0.25, 1.0)
+    assert abs(q - p["Q"]) <= 1e-13
+
+
+@pytest.mark.slow
+def test_spectral_hard_spheres_matches_sigma_form():
+    # The whole chain (phi_R, psi_R, angular rule, B~ = 4C, Fourier normalisation,
+    # padding) against eq. boltzmann evaluated by brute force (no spectral method).
+    # Angular quadrature error is O(A^-2): 16 x 16 directions leave ~1e-3.
+    with open(os.path.join(GOLDEN, "sigma_form_hard_spheres.json")) as fh:
+        gold = json.load(fh)
+    n, L = gold["n"], gold["L"]
+    f = sum(fks_inputs.maxwellian_on_grid(n, L, [c[0]], [c[1]], [c[2]])[0] for c in gold["components"])
+    plan = make_plan(n, L, 6.0, a1=16, a2=16, C=0.25)
+    Q = collide_fast(f, plan)
+    qmax = max(abs(p["Q"]) for p in gold["points"])
+    for p in gold["points"]:
+        assert abs(Q[tuple(p["index"])] - p["Q"]) <= 2e-3 * qmax
+
+
+def test_hard_sphere_loss_closed_form():
+    # Loss of Q for a Maxwellian (rho, u, T) with B = C|g|:
+    # L(v) = f(v) 4 pi C rho [sqrt(2T/pi) e^{-|w|^2/2T} + (|w| + T/|w|) erf(|w|/sqrt(2T))], w = v - u.
+    n, L = 24, 8.0
+    rho, u, T = 1.3, np.array([0.25, -0.5, 0.125]), 0.9
+    plan = make_plan(n, L, 6.0, a1=32, a2=32, C=0.25)
+    M = fks_inputs.maxwellian_on_grid(n, L, [rho], [u], [T])[0]
+    Lnum = loss_field(M, plan)
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    w = np.linalg.norm(V - u, axis=-1)
+    wsafe = np.maximum(w, 1e-300)
+    mean_g = np.sqrt(2 * T / np.pi) * np.exp(-w ** 2 / (2 * T)) + (w + T / wsafe) * special.erf(w / np.sqrt(2 * T))
+    Lex = M * 4 * np.pi * 0.25 * rho * mean_g
+    core = w < 2.0
+    err = np.abs(Lnum - Lex)[core].max() / np.abs(Lex).max()
+    assert err < 1e-3
+
+
+def test_maxwell_molecule_loss_is_rho_f():
+    # B = C = 1/(4 pi): collision frequency is 4 pi C rho = rho
+    n, L = 16, 8.0
+    rho, u, T = 0.8, np.array([0.3, 0.0, -0.2]), 1.0
+    plan = make_plan(n, L, 6.0, kernel=VHS, alpha=0.0, C=1 / (4 * np.pi), a1=8, a2=8, n_radial=16)
+    M = fks_inputs.maxwellian_on_grid(n, L, [rho], [u], [T])[0]
+    Lnum = loss_field(M, plan)
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    core = np.linalg.norm(V - u, axis=-1) < 2.5
+    assert np.abs(Lnum - rho * M)[core].max() / np.abs(rho * M).max() < 1e-2
+
+
+def test_equilibrium_and_conservation_improve_with_n():
+    # Q(M, M) ~ 0 and the momentum/energy moments of Q are spectrally small
+    L, R = 8.0, 6.0
+    eq, mom = [], []
+    for n in (16, 24, 32):
+        plan = make_plan(n, L, R, a1=4, a2=4, C=0.25)
+        M = fks_inputs.maxwellian_on_grid(n, L, [1.0], [[0.3, -0.2, 0.1]], [1.0])[0]
+        eq.append(np.linalg.norm(collide_fast(M, plan)) / np.linalg.norm(loss_field(M, plan)))
+        f = fks_inputs.maxwellian_mixture(n, L, 1, seed=3)[0]
+        Q = collide_fast(f, plan)
+        U = moments(Q, plan.grid)
+        scale = np.abs(Q).sum() * plan.grid.dv ** 3
+        mom.append((np.abs(U[1:4]).max() / scale, abs(U[4]) / scale))
+    assert eq[0] > eq[1] > eq[2] and eq[2] < 1e-6
+    # momentum: spectral convergence in n; energy: bounded by the velocity-box
+    # truncation of the |v|^2 weight (does not improve with n at fixed L)
+    assert mom[0][0] > mom[1][0] > mom[2][0] and mom[2][0] < 1e-4
+    assert max(m[1] for m in mom[1:]) < 1e-3
+
+
+def test_bkw_formula_against_sigma_form():
+    # The BKW closed form (not in the paper) checked against eq. boltzmann by brute force.
+    t0 = 5.5
+    fun = lambda p: bkw.f_bkw(t0, p)
+    for v in (np.zeros(3), np.array([1.0, -0.5, 0.3])):
+        q = sigma_form.collision_integral(fun, v, 1 / (4 * np.pi), 0.0)
+        assert abs(q - bkw.dfdt_bkw(t0, v)) <= 1e-10
+    v = np.array([0.7, 0.2, -0.4])
+    h = 1e-5
+    fd = (bkw.f_bkw(t0 + h, v) - bkw.f_bkw(t0 - h, v)) / (2 * h)
+    assert abs(fd - bkw.dfdt_bkw(t0, v)) <= 1e-9
+
+
+@pytest.mark.slow
+def test_maxwell_tables_converge_to_bkw():
+    # Spectral Q(f_BKW) -> d f_BKW/dt; the error is angular-quadrature limited, O(A^-2)
+    t0, n, L, R = 5.5, 32, 8.0, 6.0
+    f = fks_inputs.bkw_initial(n, L, t0)
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    ref = bkw.dfdt_bkw(t0, V)
+    errs = []
+    for a in (4, 8):
+        plan = make_plan(n, L, R, kernel=VHS, alpha=0.0, C=1 / (4 * np.pi), a1=a, a2=a, n_radial=8)
+        Q = collide_fast(f, plan)
+        errs.append(np.abs(Q - ref).max() / np.abs(ref).max())
+    assert errs[0] < 0.035 and errs[1] < 0.012 and errs[0] / errs[1] > 2.5
+
+
+def test_moments_of_a_maxwellian():
+    # rho, rho u, E = rho |u|^2 / 2 + 3 rho T / 2 (Section 2 macroscopic variables)
+    from oracle.grid import make_grid
+    n, L = 32, 8.0
+    rho, u, T = 1.2, np.array([0.3, -0.4, 0.2]), 0.8
+    M = fks_inputs.maxwellian_on_grid(n, L, [rho], [u], [T])[0]
+    U = moments(M, make_grid(n, L), exact=True)
+    ref = np.array([rho, *(rho * u), 0.5 * rho * u @ u + 1.5 * rho * T])
+    np.testing.assert_allclose(U, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_heun_is_second_order_exact_on_linear_decay():
+    from oracle.integrators import euler, heun
+    f = np.array([1.0, 2.0])
+    dt = 0.1
+    np.testing.assert_allclose(heun(f, lambda g: -g, dt), f * (1 - dt + dt * dt / 2), rtol=1e-15)
+    np.testing.assert_allclose(euler(f, -f, dt), f * (1 - dt), rtol=1e-15)
+
+
+def test_sigma_form_vanishes_at_equilibrium():
+    fun = sigma_form.maxwellian(1.0, (0.2, 0.1, -0.3), 0.9)
+    for v in (np.array([0.0, 0.0, 0.0]), np.array([1.0, -0.5, 0.5])):
+        loss_only = sigma_form.collision_integral(lambda p: fun(p), v, 0.25, 1.0)
+        assert abs(loss_only) <= 1e-12
