@@ -1,0 +1,177 @@
+"""Benchmark of the batched fast spectral collision operator Q(f, f) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f64]
+
+Workload (the metric's N = 32 configuration): 4096 independent cells, hard-sphere
+kernel (B~ = 1, C = 1/4), velocity grid n = 32 on [-8, 8)^3, Carleman radius R = 6,
+M = 16 directions (4 x 4), padded grid P = 48, FP32 transforms.  Each f is a seeded
+two-Maxwellian mixture (densities U[0.5,1.5], mean velocities N(0,1)^3, temperatures
+U[0.5,2], seed 1701).  One step = one Q evaluation of every cell (forward transform,
+17 gain/loss convolution terms, Galerkin truncation, synthesis).  Inputs are resident
+in HBM before timing starts.
+
+Prints one JSON line.  `value` is cells * n^3 per second.  `roofline` is for the
+dominant kernel (the slab convolution kernel), timed with hipEvents on its launch
+stream inside the timed region.  `cpu_baseline` is the FP64 oracle (O-fast) on the
+host cores, on a bounded sample of the same cells.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, L, R, A1, A2, CELLS, SEED = 32, 8.0, 6.0, 4, 4, 4096, 1701
+P = 3 * N // 2
+M = A1 * A2
+FP32_PEAK_TFLOPS = 157.3
+
+
+def flops_per_cell(n=N, p=P, m=M):
+    """Nominal algorithmic flops of one Q evaluation (5 n log2 n per complex FFT pass)."""
+    pencils = n * n + n * p + p * p
+    fwd_syn = 5 * n ** 3 * math.log2(n ** 3)                   # R2C of f + C2R of Q
+    conv = (m + 1) * 5 * p * math.log2(p) * pencils            # M directions + loss, packed
+    back = 0.5 * 5 * p * math.log2(p) * pencils                # real forward of G - L
+    pointwise = m * (4 * n ** 3 + 2 * p ** 3)
+    total = fwd_syn + conv + back + pointwise
+    slab = conv + back + pointwise                             # done by the slab kernel
+    return total, slab
+
+
+def _oracle_worker(args):
+    import scipy.fft  # noqa: F401
+    fs, plan = args
+    from oracle.collide import collide_fast
+    return [collide_fast(f, plan) for f in fs]
+
+
+def cpu_baseline(f32_cells, seconds=12.0):
+    """FP64 oracle O-fast on the host cores (one process per core), bounded sample."""
+    import multiprocessing as mp
+    from oracle import make_plan
+    plan = make_plan(N, L, R, a1=A1, a2=A2, C=0.25)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 15))
+    t0 = time.perf_counter()
+    _oracle_worker(([f32_cells[0].astype(np.float64)], plan))
+    per_cell = time.perf_counter() - t0
+    per_worker = max(1, int(seconds / max(per_cell, 1e-3)))
+    per_worker = min(per_worker, 64)
+    sample = min(cores * per_worker, len(f32_cells))
+    per_worker = max(1, sample // cores)
+    jobs = [([f32_cells[(w * per_worker + i) % len(f32_cells)].astype(np.float64) for i in range(per_worker)], plan)
+            for w in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_worker, [([jobs[0][0][0]], plan)] * cores)   # warm each worker
+        t0 = time.perf_counter()
+        pool.map(_oracle_worker, jobs)
+        wall = time.perf_counter() - t0
+    done = per_worker * cores
+    return {"value": done * N ** 3 / wall, "unit": "cells*N^3/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} of the {CELLS} cells, FP64 O-fast (scipy.fft), one process per core, "
+                      f"{wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(cells are independent, so G GPUs would each take 1/G of the cells).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch  # noqa: F401  (no device is touched before the CPU baseline has forked)
+    import fks_inputs
+
+    f64 = fks_inputs.maxwellian_mixture(N, L, CELLS, seed=SEED)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(f64[:512].astype(np.float32))
+
+    import paper_1701_01608_amd as fks
+    dev = torch.device("cuda:0")
+    f = torch.tensor(f64, dtype=torch.float32, device=dev)
+    plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=CELLS)
+    q = torch.empty_like(f)
+    for _ in range(args.warmup):
+        plan.collide(f, q)
+    torch.cuda.synchronize()
+
+    fks.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.collide(f, q)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = fks.profile_stop()
+    ms_step = wall * 1e3 / args.steps
+    value = CELLS * N ** 3 / (wall / args.steps)
+
+    # accuracy of this output on sampled cells against the FP64 oracle
+    from oracle import make_plan
+    from oracle.collide import collide_fast
+    oplan = make_plan(N, L, R, a1=A1, a2=A2, C=0.25)
+    idx = [0, 1234, 2048, CELLS - 1]
+    fs = f[idx].double().cpu().numpy()
+    ref = np.stack([collide_fast(x, oplan) for x in fs])
+    got = q[idx].double().cpu().numpy()
+    rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    total_f, slab_f = flops_per_cell()
+    slab_ms, slab_n = prof["slab"]
+    slab_avg = slab_ms / max(slab_n, 1)
+    achieved = slab_f * CELLS / (slab_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_slab<float,32>", "kernel_avg_ms": round(slab_avg, 4),
+                "flop_per_cell": round(slab_f), "cells_per_launch": CELLS}
+
+    out = {"metric": "Q(f,f) cells*N^3/s at N=32 (FP32) + rel. L2 err", "value": round(value, 1),
+           "unit": "cells*N^3/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch of 4096 cells, hard spheres, n=32, M=16 (4x4), P=48, L=8, R=6, "
+                                  "two-Maxwellian mixtures seed 1701", "cells": CELLS, "n": N, "M": M, "P": P},
+           "rel_l2": rel_l2,
+           "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]},
+           "roofline": roofline}
+
+    if not args.no_f64:
+        plan64 = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f64", max_cells=CELLS)
+        fd = torch.tensor(f64, dtype=torch.float64, device=dev)
+        qd = torch.empty_like(fd)
+        plan64.collide(fd, qd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k64 = max(1, args.steps // 2)
+        for _ in range(k64):
+            plan64.collide(fd, qd)
+        torch.cuda.synchronize()
+        w64 = (time.perf_counter() - t0) / k64
+        ref64 = np.stack([collide_fast(x, oplan) for x in fd[idx].cpu().numpy()])
+        e64 = float(np.linalg.norm(qd[idx].cpu().numpy() - ref64) / np.linalg.norm(ref64))
+        out["f64_path"] = {"value": round(CELLS * N ** 3 / w64, 1), "ms_per_step": round(w64 * 1e3, 3),
+                           "rel_l2": e64}
+        del plan64, fd, qd
+
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

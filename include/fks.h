@@ -1,0 +1,181 @@
+/*
+ * fks.h -- C ABI of libfks: the fast spectral Boltzmann collision operator and the
+ * exact-shift transport of the Fast Kinetic Scheme, on one AMD MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem:
+ *   - Q_k(f_j, f_j), the collision operator evaluated independently in every
+ *     spatial cell j on the N^3 discrete-velocity grid (Section 2.1 collision step;
+ *     Section 2.2.2; Appendix A: Fourier-Galerkin method, eq. CF1, Carleman form,
+ *     separable angular quadrature);
+ *   - the exact shift of every velocity's piecewise-constant profile by v_k dt
+ *     (Section 2.1 transport step; Section 3 particle interpretation / generic cell);
+ *   - the first-order split step: transport, then explicit Euler collision
+ *     f^{n+1} = f* + dt Q(f*) (eq. transport, eq. disc_relax).
+ *
+ * Conventions
+ *   Velocity grid: v_i = -L + i*dv, dv = 2L/n, i = 0..n-1 per axis.  A distribution
+ *   in one cell is a contiguous [n][n][n] array indexed (i, j, k) <-> (v_x, v_y, v_z),
+ *   k fastest.  A batch is [n_cells][n][n][n], cells contiguous.
+ *   Fourier modes: the symmetric set {-n/2+1, ..., n/2-1}^3 with wave numbers
+ *   xi = pi k / L; padded convolution grid P = 3n/2 per axis (alias-free).
+ *   Kernel: B = C |v - v*|^alpha (eq. J9hb, variable hard spheres); hard spheres
+ *   alpha = 1 use the closed-form separable tables, alpha < 1 (e.g. Maxwell
+ *   molecules alpha = 0) use n_radial Gauss-Legendre nodes in |x| (one separable
+ *   term per direction and node).
+ *
+ * Memory ownership
+ *   Every device buffer is allocated and owned by the caller: distributions,
+ *   outputs, the plan's table and workspace buffers, transport state, moments.
+ *   Sizes come from the *_sizes queries.  The library never calls hipMalloc or
+ *   hipFree.  Handles own host memory only.  Device pointers must be 256-byte
+ *   aligned.  *_destroy(NULL) is a no-op.
+ *
+ * Streams
+ *   `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *   device work is enqueued on it; no call synchronises the host unless stated.
+ *
+ * Errors
+ *   Every call returns fks_status.  Arguments are validated before any launch;
+ *   on error nothing is enqueued.  A batch of zero cells is a no-op (its pointers may
+ *   be NULL).  Launch failures return FKS_E_DEVICE.
+ *   fks_last_error() returns a message for the last failing call on the calling
+ *   thread (valid until that thread's next call).  Nothing throws or aborts across
+ *   this boundary.
+ */
+#ifndef FKS_H_
+#define FKS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FKS_OK = 0,
+  FKS_E_ARG = -1,         /* invalid argument (null, out of range, aliasing, alignment) */
+  FKS_E_UNSUPPORTED = -2, /* valid but not built (e.g. an n without compiled kernels) */
+  FKS_E_WORKSPACE = -3,   /* buffers not bound, or too small for n_cells */
+  FKS_E_DEVICE = -4,      /* HIP launch / copy failure */
+  FKS_E_STATE = -5        /* call out of order (e.g. collide before bind) */
+} fks_status;
+
+enum { FKS_HARD_SPHERES = 0, FKS_VHS = 1 };
+enum { FKS_F64 = 0, FKS_F32 = 1 };
+
+/* plan flags */
+#define FKS_CONSERVE 1u        /* FP64 projection of Q onto zero mass/momentum/energy */
+#define FKS_ALLOW_OVERLAP 2u   /* accept R > 4L/(3+sqrt 2) (periodic images may interact) */
+
+typedef struct {
+  int32_t n;        /* velocity points per axis; supported: 8, 12, 16, 24, 32 */
+  int32_t kernel;   /* FKS_HARD_SPHERES or FKS_VHS */
+  double L;         /* velocity box half-width: grid on [-L, L)^3, L > 0 */
+  double R;         /* Carleman truncation radius, 0 < R (<= 4L/(3+sqrt 2) unless ALLOW_OVERLAP) */
+  double alpha;     /* VHS exponent in [0, 1) for FKS_VHS; ignored for hard spheres */
+  double C;         /* kernel constant C in B = C |g|^alpha, > 0 (hard spheres: B~ = 4C) */
+  int32_t a1, a2;   /* polar x azimuthal directions (M = a1*a2), each in [1, 64] */
+  int32_t n_radial; /* radial Gauss-Legendre nodes for FKS_VHS, [1, 64]; ignored otherwise */
+  int32_t dtype;    /* FKS_F32 or FKS_F64: storage and arithmetic of the transforms */
+  uint32_t flags;   /* FKS_CONSERVE | FKS_ALLOW_OVERLAP */
+  int32_t reserved;
+} fks_collide_desc;
+
+typedef struct fks_plan_s* fks_plan;
+typedef struct fks_xport_s* fks_xport;
+
+/* ---- collision operator --------------------------------------------------------- */
+
+/* Builds the FP64 kernel tables on the host (Appendix A: phi_R, psi_R, directions,
+ * radial nodes, loss weight) for batches of up to max_cells cells (>= 1).  Host only. */
+fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_plan* out);
+
+/* Bytes of the device table buffer and of the device workspace (for max_cells cells). */
+fks_status fks_plan_sizes(fks_plan plan, size_t* table_bytes, size_t* workspace_bytes);
+
+/* Number of separable terms including the loss term, and the padded grid size P. */
+fks_status fks_plan_info(fks_plan plan, int32_t* n_terms, int32_t* pad);
+
+/* Binds caller-owned device buffers (sizes from fks_plan_sizes) and enqueues the table
+ * upload on `stream`.  May be called again to rebind. */
+fks_status fks_plan_bind(fks_plan plan, void* d_tables, size_t table_bytes, void* d_workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* q[c] = Q(f[c], f[c]) for c < n_cells (Section 2.1 collision step, Appendix A eq. CF1
+ * evaluated by the padded FFT convolution).  f, q: device [n_cells][n][n][n] of the plan
+ * dtype; q must not overlap f.  With FKS_CONSERVE, q is projected in FP64 so its discrete
+ * mass, momentum and energy vanish.  n_cells may exceed max_cells (processed in chunks). */
+fks_status fks_collide(fks_plan plan, const void* f, void* q, int64_t n_cells, void* stream);
+
+/* Explicit Euler collision stage (eq. disc_relax): f_out = f_in + dt * Q(f_in) per cell.
+ * f_out may equal f_in (in place).  q (optional, NULL to skip) receives Q.  d_moments
+ * (optional, device double [n_cells][5]) receives the FP64 moments of f_out:
+ * dv^3 sum_k (1, v_x, v_y, v_z, |v|^2/2) f_out (Section 3, macroscopic variables). */
+fks_status fks_relax(fks_plan plan, const void* f_in, void* f_out, void* q, double dt,
+                     int64_t n_cells, double* d_moments, void* stream);
+
+/* FP64 moments of f: d_u[c][0..4] = dv^3 sum_k phi(v_k) f[c][k], phi = (1, v, |v|^2/2). */
+fks_status fks_moments(fks_plan plan, const void* f, int64_t n_cells, double* d_u, void* stream);
+
+/* Uneven batch: n_groups plans (each its own n, same dtype), group g evaluates
+ * q[g] = Q(f[g]) on n_cells[g] cells.  All groups are enqueued on `stream` back to back. */
+fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const void* const* f,
+                               void* const* q, const int64_t* n_cells, void* stream);
+
+void fks_plan_destroy(fks_plan plan);
+
+/* ---- transport (Section 2.1 transport step; Section 3 generic cell) -------------- */
+
+/* Periodic box of nx*ny*nz cells of width dx (cells in C order [nx][ny][nz]) for the
+ * velocity grid (n, L).  Each velocity k keeps an FP64 sub-cell offset s_k and an
+ * integer cumulative shift o_k (device state, caller-owned). */
+fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t nz, double dx,
+                            fks_xport* out);
+
+/* Bytes of the device transport state: n^3 * (3 doubles + 3 int32 + 3 int32). */
+fks_status fks_xport_sizes(fks_xport xp, size_t* state_bytes);
+
+/* Binds the state buffer and enqueues its reset (s = 0, o = 0) on `stream`. */
+fks_status fks_xport_bind(fks_xport xp, void* d_state, size_t state_bytes, void* stream);
+
+/* One exact transport step of length dt: per velocity, t = s + v*dt,
+ * delta = floor((t + dx/2)/dx), s = t - delta*dx, o += delta (FP64, this order), then
+ * f_out[j][k] = f_in[(j - delta_k) mod box][k] for every cell j (a permutation per k).
+ * dtype is FKS_F32 or FKS_F64; f_out must not overlap f_in. */
+fks_status fks_transport(fks_xport xp, const void* f_in, void* f_out, int32_t dtype, double dt,
+                         void* stream);
+
+/* n_steps split steps (eq. transport then eq. disc_relax) on the whole box:
+ * f* = shift(f); f = f* + dt Q(f*).  f is updated in place; f_tmp is a caller buffer of
+ * the same size.  d_moments (optional, [cells][5] FP64) receives the moments after the
+ * last step.  The plan's n and dtype must match the transport's grid. */
+fks_status fks_step(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double dt,
+                    int32_t n_steps, double* d_moments, void* stream);
+
+void fks_xport_destroy(fks_xport xp);
+
+/* ---- diagnostics ------------------------------------------------------------------ */
+
+/* Per-kernel timing.  Between fks_profile_start and fks_profile_stop every kernel the
+ * library enqueues is bracketed by a pair of hipEvents recorded on its launch stream.
+ * Slots: 0 forward transform of f, 1 slab gain/loss convolutions, 2 synthesis and FP64
+ * epilogue, 3 transport offsets, 4 transport shift, 5 moments.  fks_profile_stop
+ * synchronises the recorded events (host blocks) and returns total milliseconds and
+ * launch counts per slot.  Process-wide state; not for concurrent use from several
+ * host threads. */
+typedef struct {
+  double total_ms[8];
+  int64_t launches[8];
+} fks_profile_stats;
+fks_status fks_profile_start(void);
+fks_status fks_profile_stop(fks_profile_stats* out);
+
+const char* fks_last_error(void);
+const char* fks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKS_H_ */

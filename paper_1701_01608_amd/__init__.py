@@ -1,0 +1,187 @@
+"""Python binding of libfks: the fast spectral Boltzmann collision operator Q(f, f)
+and the exact-shift transport of the Fast Kinetic Scheme on MI355X (gfx950).
+
+Every step of the computation runs in the HIP kernels behind the C ABI
+(include/fks.h).  This module only marshals arguments: torch tensors provide device
+memory and the current stream.  There is no CPU fallback; if libfks.so is missing,
+every call raises.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (FKS_ALLOW_OVERLAP, FKS_CONSERVE, FKS_F32, FKS_F64, FKS_HARD_SPHERES, FKS_VHS,  # noqa: F401
+                   FKSError)
+
+__all__ = ["Plan", "Transport", "step", "collide_grouped", "FKSError", "library_path", "profile_start",
+           "profile_stop"]
+
+_DT = {"f32": (FKS_F32, torch.float32), "f64": (FKS_F64, torch.float64)}
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+def _stream_ptr(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Plan:
+    """A collision-operator plan: FP64 host tables built by the library, device tables
+    and workspace allocated here (torch) and bound once."""
+
+    def __init__(self, n, L, R, kernel="hard_spheres", alpha=0.0, C=0.25, a1=4, a2=4, n_radial=8,
+                 dtype="f32", conserve=False, allow_overlap=False, max_cells=1024, device="cuda",
+                 stream=None):
+        L_ = _lib.lib()
+        self.n, self.L, self.R = int(n), float(L), float(R)
+        self.dtype_code, self.torch_dtype = _DT[dtype]
+        self.device = torch.device(device)
+        flags = (FKS_CONSERVE if conserve else 0) | (FKS_ALLOW_OVERLAP if allow_overlap else 0)
+        desc = _lib.CollideDesc(n=self.n, kernel=FKS_HARD_SPHERES if kernel == "hard_spheres" else FKS_VHS,
+                                L=self.L, R=self.R, alpha=float(alpha), C=float(C), a1=int(a1), a2=int(a2),
+                                n_radial=int(n_radial), dtype=self.dtype_code, flags=flags, reserved=0)
+        h = ctypes.c_void_p()
+        _lib.check(L_.fks_plan_create(ctypes.byref(desc), int(max_cells), ctypes.byref(h)))
+        self._h = h
+        self.max_cells = int(max_cells)
+        tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check(L_.fks_plan_sizes(h, ctypes.byref(tb), ctypes.byref(wb)))
+        nt, pad = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(L_.fks_plan_info(h, ctypes.byref(nt), ctypes.byref(pad)))
+        self.n_terms, self.pad = nt.value, pad.value
+        self.table_bytes, self.workspace_bytes = tb.value, wb.value
+        self.tables = torch.empty(max(tb.value, 1), dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(max(wb.value, 1), dtype=torch.uint8, device=self.device)
+        _lib.check(L_.fks_plan_bind(h, _ptr(self.tables), tb.value, _ptr(self.workspace), wb.value,
+                                    _stream_ptr(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check_f(self, f, name="f"):
+        if not (f.is_cuda and f.dtype == self.torch_dtype and f.is_contiguous()):
+            raise FKSError(-1, f"{name} must be a contiguous {self.torch_dtype} device tensor")
+        if f.dim() < 3 or tuple(f.shape[-3:]) != (self.n,) * 3:
+            raise FKSError(-1, f"{name} must have shape [..., {self.n}, {self.n}, {self.n}]")
+        return f.numel() // self.n ** 3
+
+    def collide(self, f, q=None, stream=None):
+        cells = self._check_f(f)
+        if q is None:
+            q = torch.empty_like(f)
+        self._check_f(q, "q")
+        _lib.check(_lib.lib().fks_collide(self._h, _ptr(f), _ptr(q), cells, _stream_ptr(stream)))
+        return q
+
+    def relax(self, f_in, dt, f_out=None, q=None, moments=None, stream=None):
+        cells = self._check_f(f_in, "f_in")
+        if f_out is None:
+            f_out = torch.empty_like(f_in)
+        self._check_f(f_out, "f_out")
+        if q is not None:
+            self._check_f(q, "q")
+        if moments is not None and not (moments.is_cuda and moments.dtype == torch.float64
+                                        and moments.numel() >= 5 * cells):
+            raise FKSError(-1, "moments must be a float64 device tensor with 5 entries per cell")
+        _lib.check(_lib.lib().fks_relax(self._h, _ptr(f_in), _ptr(f_out), _ptr(q), float(dt), cells,
+                                        _ptr(moments), _stream_ptr(stream)))
+        return f_out
+
+    def moments(self, f, out=None, stream=None):
+        cells = self._check_f(f)
+        if out is None:
+            out = torch.empty((cells, 5), dtype=torch.float64, device=f.device)
+        _lib.check(_lib.lib().fks_moments(self._h, _ptr(f), cells, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.fks_plan_destroy(h)
+            self._h = None
+
+
+class Transport:
+    """Exact-shift transport on a periodic box of cells (device offsets state)."""
+
+    def __init__(self, n, L, shape, dx, device="cuda", stream=None):
+        L_ = _lib.lib()
+        self.n, self.L, self.shape, self.dx = int(n), float(L), tuple(int(s) for s in shape), float(dx)
+        h = ctypes.c_void_p()
+        _lib.check(L_.fks_xport_create(self.n, self.L, *self.shape, self.dx, ctypes.byref(h)))
+        self._h = h
+        sb = ctypes.c_size_t()
+        _lib.check(L_.fks_xport_sizes(h, ctypes.byref(sb)))
+        self.state = torch.empty(sb.value, dtype=torch.uint8, device=device)
+        _lib.check(L_.fks_xport_bind(h, _ptr(self.state), sb.value, _stream_ptr(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def offsets(self):
+        """(s [nv,3] float64, o [nv,3] int32) views of the device state."""
+        nv = self.n ** 3
+        s_bytes = (nv * 24 + 255) // 256 * 256
+        s = self.state[: nv * 24].view(torch.float64).view(nv, 3)
+        o = self.state[s_bytes: s_bytes + nv * 12].view(torch.int32).view(nv, 3)
+        return s, o
+
+    def __call__(self, f_in, f_out=None, dt=0.0, stream=None):
+        if f_out is None:
+            f_out = torch.empty_like(f_in)
+        code = FKS_F32 if f_in.dtype == torch.float32 else FKS_F64
+        _lib.check(_lib.lib().fks_transport(self._h, _ptr(f_in), _ptr(f_out), code, float(dt),
+                                            _stream_ptr(stream)))
+        return f_out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.fks_xport_destroy(h)
+            self._h = None
+
+
+def step(plan, xport, f, dt, n_steps=1, f_tmp=None, moments=None, stream=None):
+    """n_steps split steps (transport, then Euler collision) in place on f."""
+    if f_tmp is None:
+        f_tmp = torch.empty_like(f)
+    _lib.check(_lib.lib().fks_step(plan.handle, xport.handle, _ptr(f), _ptr(f_tmp), float(dt), int(n_steps),
+                                   _ptr(moments), _stream_ptr(stream)))
+    return f
+
+
+def collide_grouped(plans, fs, qs=None, stream=None):
+    """Uneven batch: group g evaluates Q on fs[g] with plans[g] (one call, one stream)."""
+    g = len(plans)
+    if qs is None:
+        qs = [torch.empty_like(f) for f in fs]
+    cells = [p._check_f(f) for p, f in zip(plans, fs)]
+    VP = ctypes.c_void_p
+    arr_p = (VP * g)(*[p.handle for p in plans])
+    arr_f = (VP * g)(*[f.data_ptr() for f in fs])
+    arr_q = (VP * g)(*[q.data_ptr() for q in qs])
+    arr_n = (ctypes.c_int64 * g)(*cells)
+    _lib.check(_lib.lib().fks_collide_grouped(arr_p, g, arr_f, arr_q, arr_n, _stream_ptr(stream)))
+    return qs
+
+
+def profile_start():
+    _lib.check(_lib.lib().fks_profile_start())
+
+
+def profile_stop():
+    """{slot name: (total ms, launches)} for the launches since profile_start (host syncs)."""
+    st = _lib.ProfileStats()
+    _lib.check(_lib.lib().fks_profile_stop(ctypes.byref(st)))
+    return {name: (st.total_ms[i], st.launches[i]) for i, name in enumerate(_lib.PROFILE_SLOTS)}

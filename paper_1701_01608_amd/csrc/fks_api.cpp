@@ -1,0 +1,676 @@
+// C ABI of libfks (declared in include/fks.h): argument validation, FP64 host table
+// construction (Appendix A of the paper), workspace layout and launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fks.h"
+#include "fks_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+fks_status fail(fks_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+fks_status ok() {
+  g_err.clear();
+  return FKS_OK;
+}
+
+fks_status check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(FKS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return FKS_OK;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_m.
+void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(m, 0.0);
+  w.assign(m, 0.0);
+  for (int i = 0; i < (m + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (m + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (m == 1) p0 = 1.0, p1 = z;
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= m; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = m * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[m - 1 - i] = z;
+    w[i] = w[m - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// phi_R(s) = int_{-R}^{R} |rho| e^{i rho s} d rho = 2 R^2 [sin(x)/x - 2 sin^2(x/2)/x^2], x = R|s|
+double phi_R(double s, double R) {
+  const double x = R * std::fabs(s);
+  if (x < 1e-4) return R * R * (1.0 - x * x / 4.0);
+  const double h = std::sin(0.5 * x);
+  return 2.0 * R * R * (std::sin(x) / x - 2.0 * h * h / (x * x));
+}
+
+// psi_R(s) = int over the radius-R disc of e^{i eta.y}, |eta| = s = 2 pi R^2 J1(x)/x, x = R s
+double psi_R(double s, double R) {
+  const double x = R * std::fabs(s);
+  if (x < 1e-5) return 2.0 * kPi * R * R * (0.5 - x * x / 16.0);
+  return 2.0 * kPi * R * R * ::j1(x) / x;
+}
+
+}  // namespace
+
+namespace fks {
+namespace {
+struct ProfState {
+  bool on = false;
+  struct Rec {
+    int slot;
+    hipEvent_t b, e;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  int open_slot = -1;
+  hipEvent_t open_ev = nullptr;
+  hipError_t err = hipSuccess;
+};
+ProfState g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  const hipError_t r = hipEventCreate(&e);
+  if (r != hipSuccess && g_prof.err == hipSuccess) g_prof.err = r;
+  return e;
+}
+}  // namespace
+
+void prof_mark(int slot, bool begin, hipStream_t stream) {
+  if (!g_prof.on) return;
+  hipEvent_t e = prof_event();
+  if (!e) return;
+  const hipError_t r = hipEventRecord(e, stream);
+  if (r != hipSuccess && g_prof.err == hipSuccess) g_prof.err = r;
+  if (begin) {
+    g_prof.open_slot = slot;
+    g_prof.open_ev = e;
+  } else if (g_prof.open_slot == slot && g_prof.open_ev) {
+    g_prof.recs.push_back({slot, g_prof.open_ev, e});
+    g_prof.open_ev = nullptr;
+    g_prof.open_slot = -1;
+  } else {
+    g_prof.pool.push_back(e);
+  }
+}
+}  // namespace fks
+
+struct fks_plan_s {
+  fks_collide_desc d{};
+  int64_t max_cells = 0;
+  int n = 0, K = 0, Kh = 0;
+  int n_terms = 0;  // including the loss term
+  size_t esize = 0;
+  fks::SlabGeometry geo{};
+  std::vector<unsigned char> host_tables;  // [terms][K^3][2] in the plan dtype
+  fks::EpiParams ep{};
+  void* d_tables = nullptr;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  // workspace carve-up (byte offsets)
+  size_t off_fhat = 0, off_scr = 0, off_g = 0, off_d = 0;
+};
+
+struct fks_xport_s {
+  int n = 0, nx = 0, ny = 0, nz = 0;
+  double L = 0.0, dx = 0.0;
+  void* d_state = nullptr;
+  bool bound = false;
+};
+
+namespace {
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Separable terms in FP64: for every direction e_t (and radial node) the pair
+// (alpha_t(k), alpha'_t(k)) over the kept modes; the loss term (-1, lambda(k)) last.
+void build_tables(fks_plan_s* p, std::vector<double>& A, std::vector<double>& Ap) {
+  const fks_collide_desc& d = p->d;
+  const int K = p->K, Kh = p->Kh;
+  const size_t K3 = size_t(K) * K * K;
+  const double R = d.R;
+  std::vector<double> xi(K);
+  for (int i = 0; i < K; ++i) xi[i] = kPi * (i - Kh) / d.L;
+  struct Dir {
+    double e[3], w;
+  };
+  std::vector<Dir> dirs;
+  for (int pp = 0; pp < d.a1; ++pp)
+    for (int q = 0; q < d.a2; ++q) {
+      const double th = (pp + 0.5) * kPi / d.a1, ph = q * kPi / d.a2;
+      dirs.push_back({{std::sin(th) * std::cos(ph), std::sin(th) * std::sin(ph), std::cos(th)},
+                      kPi * kPi * std::sin(th) / (double(d.a1) * d.a2)});
+    }
+  const bool hs = d.kernel == FKS_HARD_SPHERES;
+  const int nr = hs ? 1 : d.n_radial;
+  std::vector<double> rho(nr), wrho(nr);
+  if (!hs) {
+    std::vector<double> gx, gw;
+    gauss_legendre(nr, gx, gw);
+    for (int r = 0; r < nr; ++r) {
+      rho[r] = 0.5 * R * (gx[r] + 1.0);
+      wrho[r] = 0.5 * R * gw[r];
+    }
+  }
+  // disc integral in |y| for the power-law kernel: two Gauss-Legendre panels per radial node
+  const int ng = 64;
+  std::vector<double> gx, gw;
+  gauss_legendre(ng, gx, gw);
+  const int n_dir_terms = int(dirs.size()) * nr;
+  p->n_terms = n_dir_terms + 1;
+  A.assign(size_t(p->n_terms) * K3, 0.0);
+  Ap.assign(size_t(p->n_terms) * K3, 0.0);
+  std::vector<double> yn, yw;  // per radial node: panel nodes and weights incl. 2 pi y' B~
+  for (size_t t = 0; t < dirs.size(); ++t) {
+    const Dir& D = dirs[t];
+    for (int r = 0; r < nr; ++r) {
+      const size_t term = t * nr + r;
+      double* a = &A[term * K3];
+      double* b = &Ap[term * K3];
+      if (!hs) {
+        yn.clear();
+        yw.clear();
+        const double split = std::fmin(R, 8.0 * rho[r]);
+        const double lo[2] = {0.0, split}, hi[2] = {split, R};
+        for (int pnl = 0; pnl < 2; ++pnl) {
+          if (hi[pnl] <= lo[pnl]) continue;
+          for (int i = 0; i < ng; ++i) {
+            const double y = lo[pnl] + 0.5 * (hi[pnl] - lo[pnl]) * (gx[i] + 1.0);
+            const double wy = 0.5 * (hi[pnl] - lo[pnl]) * gw[i];
+            const double bt = 4.0 * d.C * std::pow(rho[r] * rho[r] + y * y, 0.5 * (d.alpha - 1.0));
+            yn.push_back(y);
+            yw.push_back(2.0 * kPi * y * bt * wy);
+          }
+        }
+      }
+      for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j)
+          for (int l = 0; l < K; ++l) {
+            const double x0 = xi[i], x1 = xi[j], x2 = xi[l];
+            const double pr = x0 * D.e[0] + x1 * D.e[1] + x2 * D.e[2];
+            const double q0 = x0 - pr * D.e[0], q1 = x1 - pr * D.e[1], q2 = x2 - pr * D.e[2];
+            const double sp = std::sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+            const size_t m = (size_t(i) * K + j) * K + l;
+            if (hs) {
+              a[m] = phi_R(pr, R);
+              b[m] = D.w * 4.0 * d.C * psi_R(sp, R);
+            } else {
+              a[m] = 2.0 * wrho[r] * rho[r] * std::cos(rho[r] * pr);
+              double g = 0.0;
+              for (size_t u = 0; u < yn.size(); ++u) g += yw[u] * ::j0(yn[u] * sp);
+              b[m] = D.w * g;
+            }
+          }
+    }
+  }
+  // loss term: B_F(m, m) by the same quadrature, with the sign of the loss
+  double* al = &A[size_t(n_dir_terms) * K3];
+  double* bl = &Ap[size_t(n_dir_terms) * K3];
+  for (size_t m = 0; m < K3; ++m) {
+    double lam = 0.0;
+    for (int t = 0; t < n_dir_terms; ++t) lam += A[size_t(t) * K3 + m] * Ap[size_t(t) * K3 + m];
+    al[m] = -1.0;
+    bl[m] = lam;
+  }
+  // Balance the two factors of every term: (alpha, alpha') -> (s alpha, alpha'/s) leaves
+  // the product, hence Q, unchanged.  Both factors share one complex transform (real
+  // and imaginary part), so their rounding errors mix; with the loss weight lambda four
+  // orders of magnitude above 1 the small factor would lose that many digits.  s makes
+  // the two factors equally large on the spectrum of a temperature-2 Maxwellian,
+  // weight exp(-|xi|^2).
+  for (int t = 0; t < p->n_terms; ++t) {
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j)
+        for (int l = 0; l < K; ++l) {
+          const size_t m = (size_t(i) * K + j) * K + l;
+          const double w = std::exp(-(xi[i] * xi[i] + xi[j] * xi[j] + xi[l] * xi[l]));
+          sa += w * A[size_t(t) * K3 + m] * A[size_t(t) * K3 + m];
+          sb += w * Ap[size_t(t) * K3 + m] * Ap[size_t(t) * K3 + m];
+        }
+    if (!(sa > 0.0) || !(sb > 0.0)) continue;
+    const double sc = std::pow(sb / sa, 0.25);
+    for (size_t m = 0; m < K3; ++m) {
+      A[size_t(t) * K3 + m] *= sc;
+      Ap[size_t(t) * K3 + m] /= sc;
+    }
+  }
+}
+
+// (Phi Phi^T)^-1 for phi = (1, v_x, v_y, v_z, |v|^2/2) over the velocity grid.
+bool build_projection(fks_plan_s* p) {
+  const int n = p->n;
+  const double L = p->d.L, dv = 2.0 * L / n;
+  double G[5][10] = {};
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double v[3] = {-L + i * dv, -L + j * dv, -L + k * dv};
+        const double ph[5] = {1.0, v[0], v[1], v[2], 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2])};
+        for (int a = 0; a < 5; ++a)
+          for (int b = 0; b < 5; ++b) G[a][b] += ph[a] * ph[b];
+      }
+  for (int a = 0; a < 5; ++a) G[a][5 + a] = 1.0;
+  for (int c = 0; c < 5; ++c) {  // Gauss-Jordan with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < 5; ++r)
+      if (std::fabs(G[r][c]) > std::fabs(G[piv][c])) piv = r;
+    if (std::fabs(G[piv][c]) < 1e-300) return false;
+    if (piv != c)
+      for (int k = 0; k < 10; ++k) std::swap(G[c][k], G[piv][k]);
+    const double inv = 1.0 / G[c][c];
+    for (int k = 0; k < 10; ++k) G[c][k] *= inv;
+    for (int r = 0; r < 5; ++r)
+      if (r != c) {
+        const double fct = G[r][c];
+        for (int k = 0; k < 10; ++k) G[r][k] -= fct * G[c][k];
+      }
+  }
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) p->ep.minv[a * 5 + b] = G[a][5 + b];
+  p->ep.L = L;
+  p->ep.dv = dv;
+  p->ep.conserve = (p->d.flags & FKS_CONSERVE) ? 1 : 0;
+  return true;
+}
+
+fks_status check_plan_ready(const fks_plan_s* p) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (!p->bound) return fail(FKS_E_STATE, "plan buffers not bound (call fks_plan_bind)");
+  return FKS_OK;
+}
+
+// Q / Euler over n_cells cells in chunks of max_cells.
+fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, void* f_out, double dt,
+                       int64_t n_cells, double* moments, void* stream) {
+  const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
+  const int f32 = p->d.dtype == FKS_F32;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += p->max_cells) {
+    const int64_t c = (n_cells - c0 < p->max_cells) ? (n_cells - c0) : p->max_cells;
+    fks::CollideArgs a{};
+    a.f = static_cast<const unsigned char*>(f) + size_t(c0) * cell_bytes;
+    a.tables = p->d_tables;
+    a.n_terms = p->n_terms;
+    a.n_cells = c;
+    unsigned char* ws = static_cast<unsigned char*>(p->d_ws);
+    a.ws_fhat = ws + p->off_fhat;
+    a.ws_scratch = ws + p->off_scr;
+    a.ws_g = ws + p->off_g;
+    a.ws_d = ws + p->off_d;
+    a.f_in = f_in ? static_cast<const unsigned char*>(f_in) + size_t(c0) * cell_bytes : nullptr;
+    a.q = q ? static_cast<unsigned char*>(q) + size_t(c0) * cell_bytes : nullptr;
+    a.f_out = f_out ? static_cast<unsigned char*>(f_out) + size_t(c0) * cell_bytes : nullptr;
+    a.dt = dt;
+    a.moments = moments ? moments + size_t(c0) * 5 : nullptr;
+    a.ep = p->ep;
+    a.stream = stream;
+    const fks_status s = check_hip(fks::launch_collide(f32, p->n, a), "collide launch");
+    if (s != FKS_OK) return s;
+  }
+  return ok();
+}
+
+bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fks_last_error(void) { return g_err.c_str(); }
+
+fks_status fks_profile_start(void) {
+  fks::g_prof.on = true;
+  fks::g_prof.err = hipSuccess;
+  return ok();
+}
+
+fks_status fks_profile_stop(fks_profile_stats* out) {
+  if (!out) return fail(FKS_E_ARG, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  auto& P = fks::g_prof;
+  P.on = false;
+  fks_status st = FKS_OK;
+  for (auto& r : P.recs) {
+    if (st == FKS_OK) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(r.e);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.b, r.e);
+      if (e != hipSuccess) {
+        st = fail(FKS_E_DEVICE, "profile events: %s", hipGetErrorString(e));
+      } else if (r.slot >= 0 && r.slot < 8) {
+        out->total_ms[r.slot] += ms;
+        out->launches[r.slot] += 1;
+      }
+    }
+    P.pool.push_back(r.b);
+    P.pool.push_back(r.e);
+  }
+  P.recs.clear();
+  if (st == FKS_OK && P.err != hipSuccess) st = fail(FKS_E_DEVICE, "profile: %s", hipGetErrorString(P.err));
+  return st == FKS_OK ? ok() : st;
+}
+const char* fks_version(void) { return "fks 0.1 (gfx950)"; }
+
+fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_plan* out) {
+  if (!desc || !out) return fail(FKS_E_ARG, "null argument");
+  *out = nullptr;
+  const fks_collide_desc& d = *desc;
+  if (d.n < 4 || d.n % 2) return fail(FKS_E_ARG, "n must be even and >= 4 (got %d)", d.n);
+  if (!fks::collide_supported(d.n)) return fail(FKS_E_UNSUPPORTED, "n = %d has no compiled kernels", d.n);
+  if (!(d.L > 0.0) || !std::isfinite(d.L)) return fail(FKS_E_ARG, "L must be positive");
+  if (!(d.R > 0.0) || !std::isfinite(d.R)) return fail(FKS_E_ARG, "R must be positive");
+  if (!(d.flags & FKS_ALLOW_OVERLAP) && d.R > 4.0 * d.L / (3.0 + std::sqrt(2.0)) * (1.0 + 1e-12))
+    return fail(FKS_E_ARG, "R = %g exceeds the no-overlap bound 4L/(3+sqrt 2) = %g", d.R,
+                4.0 * d.L / (3.0 + std::sqrt(2.0)));
+  if (!(d.C > 0.0) || !std::isfinite(d.C)) return fail(FKS_E_ARG, "C must be positive");
+  if (d.a1 < 1 || d.a1 > 64 || d.a2 < 1 || d.a2 > 64) return fail(FKS_E_ARG, "a1, a2 must be in [1, 64]");
+  if (d.kernel != FKS_HARD_SPHERES && d.kernel != FKS_VHS) return fail(FKS_E_ARG, "unknown kernel %d", d.kernel);
+  if (d.kernel == FKS_VHS) {
+    if (d.n_radial < 1 || d.n_radial > 64) return fail(FKS_E_ARG, "n_radial must be in [1, 64]");
+    if (!(d.alpha >= 0.0 && d.alpha < 1.0)) return fail(FKS_E_ARG, "VHS alpha must be in [0, 1)");
+  }
+  if (d.dtype != FKS_F32 && d.dtype != FKS_F64) return fail(FKS_E_ARG, "dtype must be FKS_F32 or FKS_F64");
+  if (d.flags & ~(FKS_CONSERVE | FKS_ALLOW_OVERLAP)) return fail(FKS_E_ARG, "unknown flags 0x%x", d.flags);
+  if (max_cells < 1 || max_cells > (int64_t(1) << 26)) return fail(FKS_E_ARG, "max_cells out of range");
+  const int nr = d.kernel == FKS_VHS ? d.n_radial : 1;
+  if (int64_t(d.a1) * d.a2 * nr > 8192) return fail(FKS_E_ARG, "too many separable terms");
+
+  fks_plan_s* p = new (std::nothrow) fks_plan_s();
+  if (!p) return fail(FKS_E_ARG, "out of host memory");
+  p->d = d;
+  p->max_cells = max_cells;
+  p->n = d.n;
+  p->K = d.n - 1;
+  p->Kh = d.n / 2 - 1;
+  p->esize = d.dtype == FKS_F32 ? 4 : 8;
+  fks::slab_geometry(d.dtype == FKS_F32, d.n, &p->geo);
+  // the kernels address one table term block and one cell's fhat with 32-bit offsets
+  const double tab_bytes = double(int64_t(d.a1) * d.a2 * nr + 1) * p->geo.table_rows * p->geo.npair * 2 * p->esize;
+  if (tab_bytes >= 2147483648.0) {
+    delete p;
+    return fail(FKS_E_ARG, "kernel tables would exceed 2 GiB; use fewer directions or radial nodes");
+  }
+  std::vector<double> A, Ap;
+  build_tables(p, A, Ap);
+  // device layout [term][kz][half-plane pencil][2]: the kernels read the mirror pencil's
+  // values through the evenness alpha(-k) = alpha(k)
+  const int K = p->K, Kh = p->Kh, npair = p->geo.npair, rows = p->geo.table_rows;
+  const size_t K3 = size_t(K) * K * K;
+  // rows k_z = row - n/2: row 0 (Nyquist) and rows >= n stay zero
+  p->host_tables.assign(size_t(p->n_terms) * rows * npair * 2 * p->esize, 0);
+  for (size_t t = 0; t < size_t(p->n_terms); ++t)
+    for (int kzi = 0; kzi < K; ++kzi)
+      for (int pp = 0; pp < npair; ++pp) {
+        int kx, ky;
+        if (pp < Kh * K) {
+          kx = 1 + pp / K;
+          ky = pp % K - Kh;
+        } else {
+          kx = 0;
+          ky = pp - Kh * K;
+        }
+        const size_t m = (size_t(kx + Kh) * K + (ky + Kh)) * K + kzi;
+        const size_t i = ((t * rows + kzi + 1) * npair + pp) * 2;
+        if (d.dtype == FKS_F32) {
+          float* h = reinterpret_cast<float*>(p->host_tables.data());
+          h[i] = float(A[t * K3 + m]);
+          h[i + 1] = float(Ap[t * K3 + m]);
+        } else {
+          double* h = reinterpret_cast<double*>(p->host_tables.data());
+          h[i] = A[t * K3 + m];
+          h[i + 1] = Ap[t * K3 + m];
+        }
+      }
+  if (!build_projection(p)) {
+    delete p;
+    return fail(FKS_E_ARG, "singular invariant Gram matrix");
+  }
+  const size_t cs = p->esize * 2;  // complex element
+  size_t off = 0;
+  p->off_fhat = off;
+  off = round256(off + size_t(max_cells) * p->geo.fhat_elems * cs);
+  p->off_scr = off;
+  off = round256(off + size_t(max_cells) * p->geo.scratch_elems * cs);
+  p->off_g = off;
+  off = round256(off + size_t(max_cells) * p->geo.g_elems * p->esize);
+  p->off_d = off;
+  off = round256(off + size_t(max_cells) * p->geo.d_elems * cs);
+  p->ws_bytes = off;
+  *out = p;
+  return ok();
+}
+
+fks_status fks_plan_sizes(fks_plan p, size_t* table_bytes, size_t* workspace_bytes) {
+  if (!p || !table_bytes || !workspace_bytes) return fail(FKS_E_ARG, "null argument");
+  *table_bytes = p->host_tables.size();
+  *workspace_bytes = p->ws_bytes;
+  return ok();
+}
+
+fks_status fks_plan_info(fks_plan p, int32_t* n_terms, int32_t* pad) {
+  if (!p || !n_terms || !pad) return fail(FKS_E_ARG, "null argument");
+  *n_terms = p->n_terms;
+  *pad = p->geo.P;
+  return ok();
+}
+
+fks_status fks_plan_bind(fks_plan p, void* d_tables, size_t table_bytes, void* d_workspace, size_t workspace_bytes,
+                         void* stream) {
+  if (!p || !d_tables || !d_workspace) return fail(FKS_E_ARG, "null argument");
+  if (!aligned(d_tables) || !aligned(d_workspace)) return fail(FKS_E_ARG, "buffers must be 256-byte aligned");
+  if (table_bytes < p->host_tables.size())
+    return fail(FKS_E_WORKSPACE, "table buffer %zu < %zu bytes", table_bytes, p->host_tables.size());
+  if (workspace_bytes < p->ws_bytes)
+    return fail(FKS_E_WORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, p->ws_bytes);
+  fks_status s = check_hip(hipMemcpyAsync(d_tables, p->host_tables.data(), p->host_tables.size(),
+                                          hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)),
+                           "table upload");
+  if (s != FKS_OK) return s;
+  // the host copy stays alive in the plan until destroy; make the upload complete
+  // before returning so that a caller may free its stream right after binding
+  s = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "table upload sync");
+  if (s != FKS_OK) return s;
+  p->d_tables = d_tables;
+  p->d_ws = d_workspace;
+  p->bound = true;
+  return ok();
+}
+
+fks_status fks_collide(fks_plan p, const void* f, void* q, int64_t n_cells, void* stream) {
+  fks_status s = check_plan_ready(p);
+  if (s != FKS_OK) return s;
+  if (n_cells < 0) return fail(FKS_E_ARG, "n_cells < 0");
+  if (n_cells == 0) return ok();
+  if (!f || !q) return fail(FKS_E_ARG, "null f or q");
+  const size_t bytes = size_t(n_cells) * p->n * p->n * p->n * p->esize;
+  if (ranges_overlap(f, q, bytes)) return fail(FKS_E_ARG, "q must not overlap f");
+  return run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
+}
+
+fks_status fks_relax(fks_plan p, const void* f_in, void* f_out, void* q, double dt, int64_t n_cells,
+                     double* d_moments, void* stream) {
+  fks_status s = check_plan_ready(p);
+  if (s != FKS_OK) return s;
+  if (!std::isfinite(dt)) return fail(FKS_E_ARG, "dt must be finite");
+  if (n_cells < 0) return fail(FKS_E_ARG, "n_cells < 0");
+  if (n_cells == 0) return ok();
+  if (!f_in || !f_out) return fail(FKS_E_ARG, "null f_in or f_out");
+  const size_t bytes = size_t(n_cells) * p->n * p->n * p->n * p->esize;
+  if (f_in != f_out && ranges_overlap(f_in, f_out, bytes)) return fail(FKS_E_ARG, "f_out partially overlaps f_in");
+  if (q && (ranges_overlap(q, f_in, bytes) || ranges_overlap(q, f_out, bytes)))
+    return fail(FKS_E_ARG, "q must not overlap f_in or f_out");
+  return run_collide(p, f_in, f_in, q, f_out, dt, n_cells, d_moments, stream);
+}
+
+fks_status fks_moments(fks_plan p, const void* f, int64_t n_cells, double* d_u, void* stream) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (n_cells < 0) return fail(FKS_E_ARG, "n_cells < 0");
+  if (n_cells == 0) return ok();
+  if (!f || !d_u) return fail(FKS_E_ARG, "null f or d_u");
+  return check_hip(fks::launch_moments(p->d.dtype == FKS_F32, p->n, f, n_cells, d_u, p->d.L, 2.0 * p->d.L / p->n,
+                                       stream),
+                   "moments launch") == FKS_OK
+             ? ok()
+             : FKS_E_DEVICE;
+}
+
+fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const void* const* f, void* const* q,
+                               const int64_t* n_cells, void* stream) {
+  if (!plans || !f || !q || !n_cells || n_groups < 0) return fail(FKS_E_ARG, "null argument");
+  for (int g = 0; g < n_groups; ++g) {
+    fks_status s = check_plan_ready(plans[g]);
+    if (s != FKS_OK) return s;
+    if (n_cells[g] < 0 || (n_cells[g] > 0 && (!f[g] || !q[g])))
+      return fail(FKS_E_ARG, "group %d: bad buffers or count", g);
+    if (plans[g]->d.dtype != plans[0]->d.dtype) return fail(FKS_E_ARG, "groups must share one dtype");
+  }
+  for (int g = 0; g < n_groups; ++g) {
+    fks_status s = fks_collide(plans[g], f[g], q[g], n_cells[g], stream);
+    if (s != FKS_OK) return s;
+  }
+  return ok();
+}
+
+void fks_plan_destroy(fks_plan p) { delete p; }
+
+fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t nz, double dx, fks_xport* out) {
+  if (!out) return fail(FKS_E_ARG, "null out");
+  *out = nullptr;
+  if (n < 2 || n > 64) return fail(FKS_E_ARG, "n out of range");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(FKS_E_ARG, "box sizes must be >= 1");
+  if (int64_t(nx) * ny * nz > (int64_t(1) << 24)) return fail(FKS_E_ARG, "too many cells");
+  if (!(L > 0.0) || !(dx > 0.0) || !std::isfinite(L) || !std::isfinite(dx))
+    return fail(FKS_E_ARG, "L and dx must be positive");
+  fks_xport_s* x = new (std::nothrow) fks_xport_s();
+  if (!x) return fail(FKS_E_ARG, "out of host memory");
+  x->n = n;
+  x->L = L;
+  x->nx = nx;
+  x->ny = ny;
+  x->nz = nz;
+  x->dx = dx;
+  *out = x;
+  return ok();
+}
+
+fks_status fks_xport_sizes(fks_xport x, size_t* state_bytes) {
+  if (!x || !state_bytes) return fail(FKS_E_ARG, "null argument");
+  const size_t nv = size_t(x->n) * x->n * x->n;
+  *state_bytes = round256(nv * 3 * 8) + round256(nv * 3 * 4) + round256(nv * 3 * 4);
+  return ok();
+}
+
+static fks::XportState xport_state(fks_xport x) {
+  const size_t nv = size_t(x->n) * x->n * x->n;
+  unsigned char* b = static_cast<unsigned char*>(x->d_state);
+  fks::XportState st;
+  st.s = reinterpret_cast<double*>(b);
+  st.o = reinterpret_cast<int32_t*>(b + round256(nv * 3 * 8));
+  st.dl = reinterpret_cast<int32_t*>(b + round256(nv * 3 * 8) + round256(nv * 3 * 4));
+  return st;
+}
+
+fks_status fks_xport_bind(fks_xport x, void* d_state, size_t state_bytes, void* stream) {
+  if (!x || !d_state) return fail(FKS_E_ARG, "null argument");
+  if (!aligned(d_state)) return fail(FKS_E_ARG, "state must be 256-byte aligned");
+  size_t need = 0;
+  fks_xport_sizes(x, &need);
+  if (state_bytes < need) return fail(FKS_E_WORKSPACE, "state buffer %zu < %zu bytes", state_bytes, need);
+  x->d_state = d_state;
+  x->bound = true;
+  return check_hip(fks::launch_xport_reset(xport_state(x), x->n * x->n * x->n, stream), "transport reset") ==
+                 FKS_OK
+             ? ok()
+             : FKS_E_DEVICE;
+}
+
+fks_status fks_transport(fks_xport x, const void* f_in, void* f_out, int32_t dtype, double dt, void* stream) {
+  if (!x) return fail(FKS_E_ARG, "null transport");
+  if (!x->bound) return fail(FKS_E_STATE, "transport state not bound");
+  if (!f_in || !f_out) return fail(FKS_E_ARG, "null f_in or f_out");
+  if (dtype != FKS_F32 && dtype != FKS_F64) return fail(FKS_E_ARG, "bad dtype");
+  if (!std::isfinite(dt)) return fail(FKS_E_ARG, "dt must be finite");
+  const int nv = x->n * x->n * x->n;
+  const size_t bytes = size_t(x->nx) * x->ny * x->nz * nv * (dtype == FKS_F32 ? 4 : 8);
+  if (ranges_overlap(f_in, f_out, bytes)) return fail(FKS_E_ARG, "f_out must not overlap f_in");
+  const fks::XportState st = xport_state(x);
+  fks_status s = check_hip(fks::launch_xport_advance(st, x->n, x->L, dt, x->dx, stream), "transport advance");
+  if (s != FKS_OK) return s;
+  s = check_hip(fks::launch_roll(dtype == FKS_F32, f_in, f_out, st.dl, nv, x->nx, x->ny, x->nz, stream),
+                "transport roll");
+  if (s != FKS_OK) return s;
+  return ok();
+}
+
+fks_status fks_step(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt, int32_t n_steps, double* d_moments,
+                    void* stream) {
+  fks_status s = check_plan_ready(p);
+  if (s != FKS_OK) return s;
+  if (!x) return fail(FKS_E_ARG, "null transport");
+  if (!x->bound) return fail(FKS_E_STATE, "transport state not bound");
+  if (x->n != p->n || std::fabs(x->L - p->d.L) > 0.0) return fail(FKS_E_ARG, "plan and transport grids differ");
+  if (!f || !f_tmp) return fail(FKS_E_ARG, "null f or f_tmp");
+  if (n_steps < 0) return fail(FKS_E_ARG, "n_steps < 0");
+  const int64_t cells = int64_t(x->nx) * x->ny * x->nz;
+  const size_t bytes = size_t(cells) * p->n * p->n * p->n * p->esize;
+  if (ranges_overlap(f, f_tmp, bytes)) return fail(FKS_E_ARG, "f_tmp must not overlap f");
+  for (int st = 0; st < n_steps; ++st) {
+    s = fks_transport(x, f, f_tmp, p->d.dtype, dt, stream);
+    if (s != FKS_OK) return s;
+    s = run_collide(p, f_tmp, f_tmp, nullptr, f, dt, cells, st == n_steps - 1 ? d_moments : nullptr, stream);
+    if (s != FKS_OK) return s;
+  }
+  return ok();
+}
+
+void fks_xport_destroy(fks_xport x) { delete x; }
+
+}  // extern "C"

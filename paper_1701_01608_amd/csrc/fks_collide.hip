@@ -1,0 +1,651 @@
+// Batched fast spectral collision operator Q(f, f) on gfx950 (Appendix A of the paper).
+//
+// Per cell the operator is evaluated as
+//   fhat = DFT_n(f) / n^3 on the symmetric mode set K = {-n/2+1 .. n/2-1}^3      (kernel 1)
+//   for every separable term t (M directions [x radial nodes] plus the loss):
+//     Z_t = IDFT_P[ pad_P( (alpha_t + i alpha'_t) fhat ) ],   G += Re Z_t * Im Z_t (kernel 2)
+//   Qhat = DFT_P(G) / P^3 restricted to K;  Q = IDFT_n(Qhat)                       (kernel 3)
+// with P = 3n/2 (linear convolution on the kept modes, i.e. the Galerkin-truncated
+// sum of eq. CF1).  alpha_t and alpha'_t are real and even and fhat is Hermitian, so
+// Re Z_t and Im Z_t are the two real convolution factors of term t.
+//
+// Kernel 2 splits the padded grid of one cell into S slabs of Z = P/S z-planes,
+// slab r owning the planes z = r + S z'.  The first (z) inverse pass of each slab is
+// the radix-S decimation-in-frequency step folded into the input: every mode k_z is
+// multiplied by exp(2 pi i k_z r / P) and accumulated into bin k_z mod Z, followed by a
+// Z-point inverse DFT.  The remaining y and x passes run on the slab's planes only,
+// staged through LDS; G lives in a per-slab workspace accumulator.  At the end the slab
+// applies the forward x and y passes (real input, kept modes only) and a Z-point forward
+// DFT over its planes; kernel 3 combines the S slab partials with exp(-2 pi i k_z r / P)
+// (the matching decimation-in-time step), synthesises Q on the velocity grid and runs
+// the FP64 epilogue (conservation projection, Euler update, moments).
+#include <hip/hip_runtime.h>
+
+#include "fks_fft.hpp"
+#include "fks_internal.hpp"
+
+namespace fks {
+
+// Slab decomposition per (precision, n).  FP32: S slabs of Z planes so that
+// 2*Z*P <= 1024 threads each own half an x line (P/2 values, x of one parity) of the
+// slab accumulator G in registers; the LDS holds the stage buffer [Z][n-1][P+1]
+// complex.  FP64: G lives in a per-slab workspace region and 256 threads loop over
+// whole lines.
+template <typename T, int N>
+struct Cfg {
+  static constexpr int P = 3 * N / 2;
+  static constexpr int K = N - 1;
+  static constexpr int Kh = N / 2 - 1;
+  static constexpr int KH1 = Kh + 1;
+  static constexpr int WS = P + 1;
+  static constexpr int NPAIR = (K * K + 1) / 2;  // z pencils (kx, ky) of the half plane
+  static constexpr bool GREG = sizeof(T) == 4;
+  static constexpr int S = GREG ? (N >= 24 ? 6 : (N >= 16 ? 3 : 1))
+                                : (N >= 32 ? 8 : (N >= 24 ? 4 : 1));
+  static constexpr int Z = P / S;
+  static constexpr int LINES = Z * P;  // x lines (z', y) of the slab
+  // fhat / table rows: k_z = row - N/2, rows grouped in NCH chunks of Z (the fold period);
+  // row 0 (the dropped Nyquist mode) and rows >= N are zero
+  static constexpr int NCH = (N + Z - 1) / Z;
+  static constexpr int NR = NCH * Z;
+  static constexpr int NT = GREG ? ((2 * LINES + 63) / 64) * 64 : 256;
+  static constexpr size_t w_bytes = size_t(Z) * K * WS * sizeof(cpx<T>);
+  // after the last term: G staged as [LINES][P] reals, then its x spectra [Z][KH1][WS]
+  static constexpr size_t gst_bytes = GREG ? ((size_t(LINES) * P * sizeof(T) + 255) / 256) * 256 : 0;
+  static constexpr size_t spec_bytes = size_t(Z) * KH1 * WS * sizeof(cpx<T>);
+  static constexpr size_t lds_bytes = (w_bytes > gst_bytes + spec_bytes) ? w_bytes : gst_bytes + spec_bytes;
+  static_assert(P % S == 0, "slab count must divide P");
+  static_assert(P % 2 == 0, "half lines need an even P");
+  static_assert(lds_bytes <= 160 * 1024, "slab stage buffer exceeds LDS");
+  static_assert(NT <= 1024, "too many threads per slab");
+};
+
+// Raw buffer loads: one 32-bit per-lane offset plus a scalar offset per access, so an
+// unrolled sequence of strided loads needs no per-load 64-bit address registers.
+// Accesses beyond num_records bytes return 0 instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+}
+
+// exp(2 pi i q / S) for a runtime q in [0, S), from literals
+template <int S>
+__device__ __forceinline__ sc chunk_twiddle(int q) {
+  sc w = {1.0, 0.0};
+  static_for<1, S>([&](auto qq) {
+    constexpr sc c = sincos2pi(decltype(qq)::value, S);
+    if (q == decltype(qq)::value) w = c;
+  });
+  return w;
+}
+
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Half-plane z pencils: p < Kh*K -> kx = 1 + p/K, ky = p%K - Kh;  else kx = 0, ky = p - Kh*K.
+// Together with their mirrors (-kx, -ky) they cover all K^2 pencils once.
+template <int K, int Kh>
+__device__ __forceinline__ void pair_kxy(int p, int& kx, int& ky) {
+  if (p < Kh * K) {
+    kx = 1 + p / K;
+    ky = p % K - Kh;
+  } else {
+    kx = 0;
+    ky = p - Kh * K;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// kernel 1: fhat = DFT_n(f)/n^3 on the kept modes, stored for the half-plane pencils
+// only (the rest is the complex conjugate), layout [kz][pencil] so that a wavefront of
+// pencil threads reads one contiguous row per k_z.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_forward_f(const T* __restrict__ f, cpx<T>* __restrict__ fhat,
+                                                   cpx<T>* __restrict__ scratch) {
+  using C = Cfg<T, N>;
+  constexpr int K = C::K, Kh = C::Kh, NPAIR = C::NPAIR;
+  const int cell = blockIdx.x;
+  const T* fc = f + size_t(cell) * N * N * N;
+  cpx<T>* sc = scratch + size_t(cell) * N * N * N;
+  cpx<T>* fh = fhat + size_t(cell) * C::NR * NPAIR;
+  // z pass: [x][y][z] real -> sc[x][y][kz]
+  for (int it = threadIdx.x; it < N * N; it += blockDim.x) {
+    cpx<T> a[N];
+    const T* row = fc + size_t(it) * N;
+    static_for<0, N>([&](auto z) { a[z] = cpx<T>{row[z], T(0)}; });
+    dft<N, -1>(a);
+    static_for<0, K>([&](auto kz) { sc[size_t(it) * K + kz] = a[(decltype(kz)::value - Kh + N) % N]; });
+  }
+  __syncthreads();
+  // y pass: columns (x, kz)
+  for (int it = threadIdx.x; it < N * K; it += blockDim.x) {
+    const int x = it / K, kz = it % K;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto y) { a[y] = sc[(size_t(x) * N + y) * K + kz]; });
+    dft<N, -1>(a);
+    static_for<0, K>([&](auto ky) {
+      sc[(size_t(x) * N + ky) * K + kz] = a[(decltype(ky)::value - Kh + N) % N];
+    });
+  }
+  __syncthreads();
+  // x pass: columns (ky, kz) -> half-plane pencils of fhat
+  constexpr T scale = T(1.0 / (double(N) * N * N));
+  for (int it = threadIdx.x; it < K * K; it += blockDim.x) {
+    const int kyi = it / K, kzi = it % K;
+    const int ky = kyi - Kh;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto x) { a[x] = sc[(size_t(x) * N + kyi) * K + kzi]; });
+    dft<N, -1>(a);
+    static_for<0, Kh + 1>([&](auto kxv) {
+      constexpr int kx = decltype(kxv)::value;
+      if (kx > 0 || ky >= 0) {
+        const int p = kx > 0 ? (kx - 1) * K + kyi : Kh * K + ky;
+        const cpx<T> v = a[kx];
+        fh[size_t(kzi + 1) * NPAIR + p] = cpx<T>{v.re * scale, v.im * scale};
+      }
+    });
+  }
+  // zero rows: the Nyquist mode k_z = -N/2 and the chunk padding
+  for (int i = threadIdx.x; i < NPAIR; i += blockDim.x) fh[i] = cpx<T>{T(0), T(0)};
+  for (int i = threadIdx.x; i < (C::NR - N) * NPAIR; i += blockDim.x) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
+}
+
+// ------------------------------------------------------------------------------------
+// kernel 2: one slab of one cell, all separable terms
+template <typename T, int N, int RID>
+__device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T* __restrict__ tab,
+                                          int n_terms, T* __restrict__ Gw, cpx<T>* __restrict__ D,
+                                          cpx<T>* W) {
+  using C = Cfg<T, N>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
+  constexpr int NT = C::NT;
+  const int tid = threadIdx.x;
+
+  // FP32: thread tid < 2*LINES owns the half line (h, line) = divmod(tid, LINES) of G,
+  // i.e. g[j] = G[line][2j + h]; h is uniform over all but at most one wavefront
+  T g[C::GREG ? P / 2 : 1];
+  if constexpr (C::GREG) {
+    static_for<0, P / 2>([&](auto j) { g[j] = T(0); });
+  } else {
+    for (int i = tid; i < Z * P * P; i += NT) Gw[i] = T(0);
+    __syncthreads();
+  }
+
+  constexpr uint32_t row_bytes = uint32_t(NPAIR) * sizeof(cpx<T>);  // one k_z row, fhat and tables
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(fh, uint32_t(C::NR) * row_bytes);
+  const __amdgpu_buffer_rsrc_t rt = make_rsrc(tab, uint32_t(n_terms) * C::NR * row_bytes);
+  for (int t = 0; t < n_terms; ++t) {
+    const uint32_t tterm = uint32_t(t) * C::NR * row_bytes;
+    // Every stage takes an opaque copy of the thread index (opaque_tid): its index
+    // arithmetic is redone where it is used instead of being hoisted out of the term
+    // loop or shared between stages and kept live next to the accumulator (LDS plane
+    // offsets beyond the 64 KiB immediate range need their own address registers).
+    int tid = opaque_tid();
+    // stage 1: half-plane pencil p and its mirror.  Mode k_z of pencil (kx, ky) and mode
+    // -k_z of (-kx, -ky) come from the same stored value (Hermitian fhat, even tables).
+    // Rows are taken in chunks j of Z consecutive modes; with k_z = jZ + b - N/2 the
+    // slab twiddle exp(2 pi i k_z r/P) = w_S^{jr} exp(2 pi i (b - N/2) r/P): the chunk
+    // factor is one runtime scalar, the per-bin factor is applied once after the loop.
+    for (int p = tid; p < NPAIR; p += NT) {
+      int kx, ky;
+      pair_kxy<K, Kh>(p, kx, ky);
+      cpx<T> bA[Z], bB[Z];
+      static_for<0, Z>([&](auto bb) {
+        bA[bb] = cpx<T>{T(0), T(0)};
+        bB[bb] = cpx<T>{T(0), T(0)};
+      });
+      const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+      for (int j = 0; j < C::NCH; ++j) {
+        const sc wj = chunk_twiddle<C::S>((j * RID) % C::S);
+        const T cr = T(wj.c), ci = T(wj.s);
+        const uint32_t s0 = uint32_t(j) * Z * row_bytes;
+        static_for<0, Z>([&](auto bb) {
+          constexpr uint32_t sb = uint32_t(decltype(bb)::value) * row_bytes;
+          const cpx<T> fv = bload2<T>(rf, voff, s0 + sb);
+          const cpx<T> ab = bload2<T>(rt, voff, tterm + s0 + sb);
+          const T ar = ab.re * fv.re, ai = ab.re * fv.im, br = ab.im * fv.re, bi = ab.im * fv.im;
+          const cpx<T> cA = {ar - bi, ai + br};   // (a + ib) fv
+          const cpx<T> cB = {ar + bi, br - ai};   // (a + ib) conj(fv)
+          bA[bb] = bA[bb] + cpx<T>{cr * cA.re - ci * cA.im, cr * cA.im + ci * cA.re};
+          bB[bb] = bB[bb] + cpx<T>{cr * cB.re + ci * cB.im, cr * cB.im - ci * cB.re};
+        });
+      }
+      // per-bin twiddles and the bin of each partial sum (k_z mod Z, resp. -k_z mod Z)
+      cpx<T> oA[Z], oB[Z];
+      static_for<0, Z>([&](auto bb) {
+        constexpr int e = decltype(bb)::value - N / 2;
+        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA[bb]);
+        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB[bb]);
+      });
+      dft<Z, +1>(oA);
+      const int kxa = kx + Kh, kya = ky + Kh;
+      static_for<0, Z>([&](auto zp) { W[(size_t(zp) * K + kxa) * WS + kya] = oA[zp]; });
+      if (kx != 0 || ky != 0) {
+        dft<Z, +1>(oB);
+        const int kxb = Kh - kx, kyb = Kh - ky;
+        static_for<0, Z>([&](auto zp) { W[(size_t(zp) * K + kxb) * WS + kyb] = oB[zp]; });
+      }
+    }
+    __syncthreads();
+    // stage 2: y lines (z', kx): K modes -> P points, in place
+    tid = opaque_tid();
+    if constexpr (C::GREG) {
+      // half lines: work item it = h*Z*K + line computes the outputs y = 2j + h of one
+      // line; all inputs of a round are read before any output of that round is written
+      constexpr int HL = Z * K, ITEMS = 2 * HL, ROUNDS = (ITEMS + NT - 1) / NT;
+      for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int it = rd * NT + tid;
+        const bool act = it < ITEMS;
+        const int h = act ? it / HL : 0;
+        cpx<T>* row = W + size_t(act ? it - h * HL : 0) * WS;
+        cpx<T> u[P / 2];
+        if (h) {
+          if (act) fold_half<P, Kh, 1>(u, [&](int i) { return row[i]; });
+        } else {
+          if (act) fold_half<P, Kh, 0>(u, [&](int i) { return row[i]; });
+        }
+        __syncthreads();
+        if (act) {
+          dft<P / 2, +1>(u);
+          static_for<0, P / 2>([&](auto j) { row[2 * decltype(j)::value + h] = u[j]; });
+        }
+      }
+    } else {
+      for (int it = tid; it < Z * K; it += NT) {
+        cpx<T>* row = W + size_t(it) * WS;
+        cpx<T> a[P];
+        static_for<0, P>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
+        static_for<0, K>([&](auto kyi) { a[(decltype(kyi)::value - Kh + P) % P] = row[kyi]; });
+        dft<P, +1>(a);
+        static_for<0, P>([&](auto y) { row[y] = a[y]; });
+      }
+    }
+    __syncthreads();
+    // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
+    tid = opaque_tid();
+    if constexpr (C::GREG) {
+      if (tid < 2 * C::LINES) {
+        const int h = tid / C::LINES, line = tid - h * C::LINES;
+        const int zp = line / P, y = line % P;
+        const cpx<T>* col = W + size_t(zp) * K * WS + y;
+        cpx<T> u[P / 2];
+        if (h) fold_half<P, Kh, 1>(u, [&](int i) { return col[size_t(i) * WS]; });
+        else fold_half<P, Kh, 0>(u, [&](int i) { return col[size_t(i) * WS]; });
+        dft<P / 2, +1>(u);
+        static_for<0, P / 2>([&](auto j) { g[j] += u[j].re * u[j].im; });
+      }
+    } else {
+      for (int it = tid; it < Z * P; it += NT) {
+        const int zp = it / P, y = it % P;
+        cpx<T> a[P];
+        static_for<0, P>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
+        static_for<0, K>([&](auto kxi) {
+          a[(decltype(kxi)::value - Kh + P) % P] = W[(size_t(zp) * K + kxi) * WS + y];
+        });
+        dft<P, +1>(a);
+        T* gl = Gw + size_t(it) * P;
+        static_for<0, P>([&](auto x) { gl[x] += a[x].re * a[x].im; });
+      }
+    }
+    __syncthreads();
+  }
+
+  // forward x pass: real G lines (z', y) -> kx in [0, Kh] -> W[z'][kx][y]
+  cpx<T>* Wspec = W;
+  if constexpr (C::GREG) {
+    // stage the half lines as whole lines, then one thread per line takes its low modes
+    T* Gst = reinterpret_cast<T*>(W);
+    Wspec = reinterpret_cast<cpx<T>*>(reinterpret_cast<unsigned char*>(W) + C::gst_bytes);
+    if (tid < 2 * C::LINES) {
+      const int h = tid / C::LINES, line = tid - h * C::LINES;
+      static_for<0, P / 2>([&](auto j) { Gst[size_t(line) * P + 2 * decltype(j)::value + h] = g[j]; });
+    }
+    __syncthreads();
+    for (int it = tid; it < C::LINES; it += NT) {
+      const int zp = it / P, y = it % P;
+      cpx<T> o[KH1];
+      rdft_low<P, KH1>(Gst + size_t(it) * P, o);
+      static_for<0, KH1>([&](auto kx) { Wspec[(size_t(zp) * KH1 + kx) * WS + y] = o[kx]; });
+    }
+  } else {
+    for (int it = tid; it < Z * P; it += NT) {
+      const int zp = it / P, y = it % P;
+      const T* gl = Gw + size_t(it) * P;
+      cpx<T> o[KH1];
+      rdft_low<P, KH1>(gl, o);
+      static_for<0, KH1>([&](auto kx) { Wspec[(size_t(zp) * KH1 + kx) * WS + y] = o[kx]; });
+    }
+  }
+  __syncthreads();
+  // forward y pass: lines (z', kx) -> ky in K, in place
+  for (int it = tid; it < Z * KH1; it += NT) {
+    cpx<T>* row = Wspec + size_t(it) * WS;
+    cpx<T> a[P];
+    static_for<0, P>([&](auto y) { a[y] = row[y]; });
+    dft<P, -1>(a);
+    static_for<0, K>([&](auto kyi) { row[kyi] = a[(decltype(kyi)::value - Kh + P) % P]; });
+  }
+  __syncthreads();
+  // Z-point forward DFT over the slab planes -> D[kx][ky][b]
+  for (int it = tid; it < KH1 * K; it += NT) {
+    const int kx = it / K, ky = it % K;
+    cpx<T> a[Z];
+    static_for<0, Z>([&](auto zp) { a[zp] = Wspec[(size_t(zp) * KH1 + kx) * WS + ky]; });
+    dft<Z, -1>(a);
+    static_for<0, Z>([&](auto b) { D[size_t(it) * Z + b] = a[b]; });
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((Cfg<T, N>::NT)) void k_slab(const cpx<T>* __restrict__ fhat,
+                                                        const T* __restrict__ tab, int n_terms,
+                                                        T* __restrict__ G, cpx<T>* __restrict__ D,
+                                                        int xcd_map) {
+  using C = Cfg<T, N>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cpx<T>* W = reinterpret_cast<cpx<T>*>(lds_raw);
+  // Workgroups are dealt round-robin to the 8 XCDs; with xcd_map the S slabs of one cell
+  // land on the same XCD (consecutive in its queue) so they share fhat through its L2.
+  const int b = blockIdx.x;
+  int cell, r;
+  if (xcd_map) {
+    const int j = b >> 3;
+    cell = (j / C::S) * 8 + (b & 7);
+    r = j % C::S;
+  } else {
+    cell = b / C::S;
+    r = b % C::S;
+  }
+  const cpx<T>* fh = fhat + size_t(cell) * C::NR * C::NPAIR;
+  T* Gs = C::GREG ? nullptr : G + (size_t(cell) * C::S + r) * (size_t(C::Z) * C::P * C::P);
+  cpx<T>* Ds = D + (size_t(cell) * C::S + r) * (size_t(C::KH1) * C::K * C::Z);
+  static_for<0, C::S>([&](auto rid) {
+    if (r == decltype(rid)::value) slab_body<T, N, decltype(rid)::value>(fh, tab, n_terms, Gs, Ds, W);
+  });
+}
+
+// ------------------------------------------------------------------------------------
+// kernel 3: combine slabs, synthesise Q on the velocity grid, FP64 epilogue
+__device__ __forceinline__ void block_reduce5(double (&v)[5], double* red) {
+  // red: LDS [5][NT/64]; result broadcast to all threads
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  static_for<0, 5>([&](auto i) {
+    double x = v[i];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[i * 16 + wid] = x;
+  });
+  __syncthreads();
+  static_for<0, 5>([&](auto i) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[i * 16 + w];
+    v[i] = s;
+  });
+  __syncthreads();
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cpx<T>* __restrict__ scratch,
+                                                const T* f_in, T* q, T* f_out, double dt,
+                                                double* __restrict__ moments, EpiParams ep) {
+  using C = Cfg<T, N>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, Z = C::Z, S = C::S;
+  constexpr size_t N3 = size_t(N) * N * N;
+  __shared__ double red[5 * 16];
+  const int cell = blockIdx.x;
+  const cpx<T>* Dc = D + size_t(cell) * S * (size_t(KH1) * K * Z);
+  cpx<T>* sc = scratch + size_t(cell) * N3;
+  T* Qtmp = reinterpret_cast<T*>(sc + size_t(KH1) * N * N);  // N^3 reals after the spectra
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr double inv_p3 = 1.0 / (double(P) * P * P);
+
+  // combine the S slab partials for every kept (kx >= 0, ky, kz), then z synthesis
+  for (int it = tid; it < KH1 * K; it += nt) {
+    const int kx = it / K, ky = it % K;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto z) { a[z] = cpx<T>{T(0), T(0)}; });
+    static_for<0, K>([&](auto kzi) {
+      constexpr int kz = decltype(kzi)::value - Kh;
+      constexpr int b = ((kz % Z) + Z) % Z;
+      cpx<T> acc = {T(0), T(0)};
+      static_for<0, S>([&](auto r) {
+        const cpx<T> d = Dc[(size_t(decltype(r)::value) * KH1 * K + it) * Z + b];
+        acc = acc + twiddle<P, -1, long(kz) * decltype(r)::value>(d);
+      });
+      a[(kz + N) % N] = cpx<T>{T(acc.re * T(inv_p3)), T(acc.im * T(inv_p3))};
+    });
+    dft<N, +1>(a);
+    static_for<0, N>([&](auto z) { sc[(size_t(kx) * N + ky) * N + z] = a[z]; });
+  }
+  __syncthreads();
+  // y synthesis: columns (kx >= 0, z), in place ky -> y
+  for (int it = tid; it < KH1 * N; it += nt) {
+    const int kx = it / N, z = it % N;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
+    static_for<0, K>([&](auto kyi) {
+      a[(decltype(kyi)::value - Kh + N) % N] = sc[(size_t(kx) * N + kyi) * N + z];
+    });
+    dft<N, +1>(a);
+    static_for<0, N>([&](auto y) { sc[(size_t(kx) * N + y) * N + z] = a[y]; });
+  }
+  __syncthreads();
+  // x synthesis (Hermitian in kx) -> real Q; FP64 invariant moments of Q
+  double m[5] = {0, 0, 0, 0, 0};
+  for (int it = tid; it < N * N; it += nt) {
+    const int y = it / N, z = it % N;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
+    static_for<0, KH1>([&](auto kx) {
+      const cpx<T> v = sc[(size_t(kx) * N + y) * N + z];
+      a[kx] = v;
+      if constexpr (decltype(kx)::value > 0) a[N - decltype(kx)::value] = conj(v);
+    });
+    dft<N, +1>(a);
+    const double vy = -ep.L + y * ep.dv, vz = -ep.L + z * ep.dv;
+    static_for<0, N>([&](auto x) {
+      const T qv = a[x].re;
+      Qtmp[(size_t(x) * N + y) * N + z] = qv;
+      const double vx = -ep.L + decltype(x)::value * ep.dv;
+      const double d = double(qv);
+      m[0] += d;
+      m[1] += vx * d;
+      m[2] += vy * d;
+      m[3] += vz * d;
+      m[4] += 0.5 * (vx * vx + vy * vy + vz * vz) * d;
+    });
+  }
+  __syncthreads();
+  double lam[5] = {0, 0, 0, 0, 0};
+  if (ep.conserve) {
+    block_reduce5(m, red);
+    for (int i = 0; i < 5; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < 5; ++j) s += ep.minv[i * 5 + j] * m[j];
+      lam[i] = s;
+    }
+  }
+  // correct, write Q and/or the Euler update, moments of the result
+  const T* fi = f_in ? f_in + size_t(cell) * N3 : nullptr;
+  T* qo = q ? q + size_t(cell) * N3 : nullptr;
+  T* fo = f_out ? f_out + size_t(cell) * N3 : nullptr;
+  double u[5] = {0, 0, 0, 0, 0};
+  for (size_t i = tid; i < N3; i += nt) {
+    const int x = int(i / (N * N)), y = int((i / N) % N), z = int(i % N);
+    const double vx = -ep.L + x * ep.dv, vy = -ep.L + y * ep.dv, vz = -ep.L + z * ep.dv;
+    const double e = 0.5 * (vx * vx + vy * vy + vz * vz);
+    double qv = double(Qtmp[i]);
+    if (ep.conserve) qv -= lam[0] + lam[1] * vx + lam[2] * vy + lam[3] * vz + lam[4] * e;
+    if (qo) qo[i] = T(qv);
+    if (fo) {
+      const T nv = T(double(fi[i]) + dt * qv);
+      fo[i] = nv;
+      const double d = double(nv);
+      u[0] += d;
+      u[1] += vx * d;
+      u[2] += vy * d;
+      u[3] += vz * d;
+      u[4] += e * d;
+    }
+  }
+  if (moments && fo) {
+    block_reduce5(u, red);
+    if (tid == 0) {
+      const double w = ep.dv * ep.dv * ep.dv;
+      for (int i = 0; i < 5; ++i) moments[size_t(cell) * 5 + i] = u[i] * w;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// FP64 moments of f: dv^3 sum phi(v) f
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_moments(const T* __restrict__ f, double* __restrict__ u_out,
+                                                 double L, double dv) {
+  constexpr size_t N3 = size_t(N) * N * N;
+  __shared__ double red[5 * 16];
+  const int cell = blockIdx.x;
+  const T* fc = f + size_t(cell) * N3;
+  double u[5] = {0, 0, 0, 0, 0};
+  for (size_t i = threadIdx.x; i < N3; i += blockDim.x) {
+    const int x = int(i / (N * N)), y = int((i / N) % N), z = int(i % N);
+    const double vx = -L + x * dv, vy = -L + y * dv, vz = -L + z * dv;
+    const double d = double(fc[i]);
+    u[0] += d;
+    u[1] += vx * d;
+    u[2] += vy * d;
+    u[3] += vz * d;
+    u[4] += 0.5 * (vx * vx + vy * vy + vz * vz) * d;
+  }
+  block_reduce5(u, red);
+  if (threadIdx.x == 0) {
+    const double w = dv * dv * dv;
+    for (int i = 0; i < 5; ++i) u_out[size_t(cell) * 5 + i] = u[i] * w;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// host launchers
+template <typename T, int N>
+static hipError_t launch_collide_impl(const CollideArgs& a) {
+  using C = Cfg<T, N>;
+  const T* f = static_cast<const T*>(a.f);
+  cpx<T>* fhat = static_cast<cpx<T>*>(a.ws_fhat);
+  cpx<T>* scr = static_cast<cpx<T>*>(a.ws_scratch);
+  T* G = static_cast<T*>(a.ws_g);
+  cpx<T>* D = static_cast<cpx<T>*>(a.ws_d);
+  hipStream_t st = static_cast<hipStream_t>(a.stream);
+  const int cells = int(a.n_cells);
+  static bool lds_attr_set = false;  // dynamic LDS above 64 KB must be opted into per kernel
+  if (!lds_attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_slab<T, N>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(C::lds_bytes));
+    if (e != hipSuccess) return e;
+    lds_attr_set = true;
+  }
+  prof_mark(kProfForward, true, st);
+  hipLaunchKernelGGL((k_forward_f<T, N>), dim3(cells), dim3(256), 0, st, f, fhat, scr);
+  prof_mark(kProfForward, false, st);
+  prof_mark(kProfSlab, true, st);
+  hipLaunchKernelGGL((k_slab<T, N>), dim3(cells * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
+                     static_cast<const T*>(a.tables), a.n_terms, G, D, (cells % 8 == 0) ? 1 : 0);
+  prof_mark(kProfSlab, false, st);
+  prof_mark(kProfFinish, true, st);
+  hipLaunchKernelGGL((k_finish<T, N>), dim3(cells), dim3(256), 0, st, D, scr,
+                     static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
+                     a.moments, a.ep);
+  prof_mark(kProfFinish, false, st);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t launch_moments_impl(const void* f, int64_t cells, double* u, double L, double dv,
+                                      void* stream) {
+  prof_mark(kProfMoments, true, static_cast<hipStream_t>(stream));
+  hipLaunchKernelGGL((k_moments<T, N>), dim3(int(cells)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const T*>(f), u, L, dv);
+  prof_mark(kProfMoments, false, static_cast<hipStream_t>(stream));
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static void sizes_impl(SlabGeometry* g) {
+  using C = Cfg<T, N>;
+  g->P = C::P;
+  g->S = C::S;
+  g->Z = C::Z;
+  g->fhat_elems = size_t(C::NR) * C::NPAIR;
+  g->table_rows = C::NR;
+  g->scratch_elems = size_t(N) * N * N;
+  g->g_elems = C::GREG ? 1 : size_t(C::S) * C::Z * C::P * C::P;
+  g->npair = C::NPAIR;
+  g->d_elems = size_t(C::S) * C::KH1 * C::K * C::Z;
+}
+
+#define FKS_DISPATCH_N(T, n, CALL) \
+  switch (n) {                     \
+    case 8: return CALL(T, 8);     \
+    case 12: return CALL(T, 12);   \
+    case 16: return CALL(T, 16);   \
+    case 24: return CALL(T, 24);   \
+    case 32: return CALL(T, 32);   \
+    default: break;                \
+  }
+
+bool collide_supported(int n) { return n == 8 || n == 12 || n == 16 || n == 24 || n == 32; }
+
+hipError_t launch_collide(int dtype_is_f32, int n, const CollideArgs& a) {
+#define CALL_C(T, nn) launch_collide_impl<T, nn>(a)
+  if (dtype_is_f32) {
+    FKS_DISPATCH_N(float, n, CALL_C)
+  } else {
+    FKS_DISPATCH_N(double, n, CALL_C)
+  }
+#undef CALL_C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments(int dtype_is_f32, int n, const void* f, int64_t cells, double* u, double L,
+                          double dv, void* stream) {
+#define CALL_M(T, nn) launch_moments_impl<T, nn>(f, cells, u, L, dv, stream)
+  if (dtype_is_f32) {
+    FKS_DISPATCH_N(float, n, CALL_M)
+  } else {
+    FKS_DISPATCH_N(double, n, CALL_M)
+  }
+#undef CALL_M
+  return hipErrorInvalidValue;
+}
+
+void slab_geometry(int dtype_is_f32, int n, SlabGeometry* g) {
+#define CALL_G(T, nn) sizes_impl<T, nn>(g)
+  if (dtype_is_f32) {
+    switch (n) {
+      case 8: CALL_G(float, 8); return;
+      case 12: CALL_G(float, 12); return;
+      case 16: CALL_G(float, 16); return;
+      case 24: CALL_G(float, 24); return;
+      case 32: CALL_G(float, 32); return;
+    }
+  } else {
+    switch (n) {
+      case 8: CALL_G(double, 8); return;
+      case 12: CALL_G(double, 12); return;
+      case 16: CALL_G(double, 16); return;
+      case 24: CALL_G(double, 24); return;
+      case 32: CALL_G(double, 32); return;
+    }
+  }
+#undef CALL_G
+}
+
+}  // namespace fks

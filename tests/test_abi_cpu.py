@@ -1,0 +1,103 @@
+"""The C-ABI library loads on a CPU host, exports every symbol include/fks.h declares,
+and validates arguments in host-only calls (no device work)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fks.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fks_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1701_01608_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfks.so is not built (python -m paper_1701_01608_amd.build)")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(lib):
+    h = ctypes.CDLL(lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(h, n), n
+    assert set(names) == set(lib.EXPORTS)
+
+
+def _desc(lib, **kw):
+    d = dict(n=16, kernel=lib.FKS_HARD_SPHERES, L=8.0, R=6.0, alpha=0.0, C=0.25, a1=4, a2=4, n_radial=8,
+             dtype=lib.FKS_F32, flags=0, reserved=0)
+    d.update(kw)
+    return lib.CollideDesc(**d)
+
+
+def _create(lib, desc, max_cells=4):
+    h = ctypes.c_void_p()
+    st = lib.lib().fks_plan_create(ctypes.byref(desc), max_cells, ctypes.byref(h))
+    return st, h
+
+
+def test_plan_create_sizes_and_destroy(lib):
+    L = lib.lib()
+    st, h = _create(lib, _desc(lib))
+    assert st == 0, L.fks_last_error()
+    tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.fks_plan_sizes(h, ctypes.byref(tb), ctypes.byref(wb)) == 0
+    nt, pad = ctypes.c_int32(), ctypes.c_int32()
+    assert L.fks_plan_info(h, ctypes.byref(nt), ctypes.byref(pad)) == 0
+    assert nt.value == 17 and pad.value == 24
+    # [terms][rows][pencils][2]: rows = k_z chunks of the slab fold, pencils = half plane
+    assert tb.value % (17 * ((15 * 15 + 1) // 2) * 2 * 4) == 0 and tb.value >= 17 * 15 * 113 * 8
+    assert wb.value > 0
+    L.fks_plan_destroy(h)
+    L.fks_plan_destroy(None)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(n=10), -2), (dict(n=7), -1), (dict(L=-1.0), -1), (dict(R=7.5), -1), (dict(a1=0), -1),
+    (dict(kernel=5), -1), (dict(dtype=3), -1), (dict(flags=64), -1), (dict(C=0.0), -1),
+    (dict(kernel=1, n_radial=0), -1), (dict(kernel=1, alpha=1.0), -1),
+])
+def test_plan_create_rejects(lib, bad, status):
+    st, h = _create(lib, _desc(lib, **bad))
+    assert st == status
+    assert h.value is None
+    assert lib.lib().fks_last_error()
+
+
+def test_overlap_flag_allows_large_R(lib):
+    st, h = _create(lib, _desc(lib, R=7.5, flags=lib.FKS_ALLOW_OVERLAP))
+    assert st == 0
+    lib.lib().fks_plan_destroy(h)
+
+
+def test_calls_before_bind_fail_cleanly(lib):
+    L = lib.lib()
+    st, h = _create(lib, _desc(lib))
+    assert st == 0
+    assert L.fks_collide(h, ctypes.c_void_p(256), ctypes.c_void_p(512 * 1024 * 1024), 1, None) == -5
+    assert b"bind" in L.fks_last_error()
+    L.fks_plan_destroy(h)
+    assert L.fks_collide(None, None, None, 1, None) == -1
+
+
+def test_transport_create_validation(lib):
+    L = lib.lib()
+    h = ctypes.c_void_p()
+    assert L.fks_xport_create(16, 8.0, 0, 4, 4, 0.1, ctypes.byref(h)) == -1
+    assert L.fks_xport_create(16, 8.0, 4, 4, 4, -0.1, ctypes.byref(h)) == -1
+    assert L.fks_xport_create(16, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) == 0
+    sb = ctypes.c_size_t()
+    assert L.fks_xport_sizes(h, ctypes.byref(sb)) == 0 and sb.value >= 16 ** 3 * 48
+    assert L.fks_transport(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1, 0.1, None) == -5
+    L.fks_xport_destroy(h)
