@@ -32,6 +32,17 @@ N, L, R, A1, A2, CELLS, SEED = 32, 8.0, 6.0, 4, 4, 4096, 1701
 P = 3 * N // 2
 M = A1 * A2
 FP32_PEAK_TFLOPS = 157.3
+# HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
+# for the kernel sources with this hash, otherwise the traffic field is reported as null.
+SLAB_TRAFFIC = {"sha": "0f495a90a493ba6e", "bytes": 2064841104}
+
+
+def kernel_sources_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1701_01608_amd", "csrc")
+    src = open(os.path.join(d, "fks_collide.hip"), "rb").read() + open(os.path.join(d, "fks_fft.hpp"), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
 
 
 def flops_per_cell(n=N, p=P, m=M):
@@ -88,7 +99,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": {"read": nbytes, "write": nbytes}, "launches": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(cells are independent, so G GPUs would each take 1/G of the cells).", file=sys.stderr)
@@ -135,8 +158,9 @@ def main():
     slab_ms, slab_n = prof["slab"]
     slab_avg = slab_ms / max(slab_n, 1)
     achieved = slab_f * CELLS / (slab_avg * 1e-3) / 1e12
+    traffic = SLAB_TRAFFIC["bytes"] if kernel_sources_hash() == SLAB_TRAFFIC["sha"] else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_slab<float,32>", "kernel_avg_ms": round(slab_avg, 4),
                 "flop_per_cell": round(slab_f), "cells_per_launch": CELLS}
 

@@ -115,6 +115,13 @@ fks_status fks_collide(fks_plan plan, const void* f, void* q, int64_t n_cells, v
 fks_status fks_relax(fks_plan plan, const void* f_in, void* f_out, void* q, double dt,
                      int64_t n_cells, double* d_moments, void* stream);
 
+/* n_steps Heun (SSP-RK2) steps of the space-homogeneous collision equation df/dt = Q(f)
+ * in place on f (the paper allows other integrators in place of eq. disc_relax):
+ * f1 = f + dt Q(f);  f2 = f1 + dt Q(f1);  f = (f + f2)/2.  f_tmp1, f_tmp2: caller buffers of
+ * the size of f, not overlapping f or each other. */
+fks_status fks_heun(fks_plan plan, void* f, void* f_tmp1, void* f_tmp2, double dt, int32_t n_steps,
+                    int64_t n_cells, void* stream);
+
 /* FP64 moments of f: d_u[c][0..4] = dv^3 sum_k phi(v_k) f[c][k], phi = (1, v, |v|^2/2). */
 fks_status fks_moments(fks_plan plan, const void* f, int64_t n_cells, double* d_u, void* stream);
 
@@ -154,6 +161,20 @@ fks_status fks_step(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double dt
                     int32_t n_steps, double* d_moments, void* stream);
 
 void fks_xport_destroy(fks_xport xp);
+
+/* ---- stream capture ---------------------------------------------------------------- */
+
+/* Records every library call enqueued on `stream` between fks_graph_begin and
+ * fks_graph_end into one hipGraph (no device work runs while recording), so that a
+ * launch-bound sequence (e.g. many small Q evaluations or split steps) is replayed with
+ * one fks_graph_launch.  Buffers and plans used in the recording must stay alive and
+ * unchanged while the graph exists.  No library call synchronises the host while
+ * recording, except fks_plan_bind and fks_profile_stop, which must not be recorded. */
+typedef struct fks_graph_s* fks_graph;
+fks_status fks_graph_begin(void* stream);
+fks_status fks_graph_end(void* stream, fks_graph* out);
+fks_status fks_graph_launch(fks_graph graph, void* stream);
+void fks_graph_destroy(fks_graph graph);
 
 /* ---- diagnostics ------------------------------------------------------------------ */
 

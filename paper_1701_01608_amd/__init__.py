@@ -16,7 +16,7 @@ from ._lib import (FKS_ALLOW_OVERLAP, FKS_CONSERVE, FKS_F32, FKS_F64, FKS_HARD_S
                    FKSError)
 
 __all__ = ["Plan", "Transport", "step", "collide_grouped", "FKSError", "library_path", "profile_start",
-           "profile_stop"]
+           "profile_stop", "Graph"]
 
 _DT = {"f32": (FKS_F32, torch.float32), "f64": (FKS_F64, torch.float64)}
 
@@ -96,6 +96,15 @@ class Plan:
         _lib.check(_lib.lib().fks_relax(self._h, _ptr(f_in), _ptr(f_out), _ptr(q), float(dt), cells,
                                         _ptr(moments), _stream_ptr(stream)))
         return f_out
+
+    def heun(self, f, dt, n_steps=1, tmp=None, stream=None):
+        """n_steps Heun steps of df/dt = Q(f) in place on f (device scratch tmp: 2 buffers)."""
+        cells = self._check_f(f)
+        if tmp is None:
+            tmp = (torch.empty_like(f), torch.empty_like(f))
+        _lib.check(_lib.lib().fks_heun(self._h, _ptr(f), _ptr(tmp[0]), _ptr(tmp[1]), float(dt), int(n_steps),
+                                       cells, _stream_ptr(stream)))
+        return f
 
     def moments(self, f, out=None, stream=None):
         cells = self._check_f(f)
@@ -185,3 +194,37 @@ def profile_stop():
     st = _lib.ProfileStats()
     _lib.check(_lib.lib().fks_profile_stop(ctypes.byref(st)))
     return {name: (st.total_ms[i], st.launches[i]) for i, name in enumerate(_lib.PROFILE_SLOTS)}
+
+
+class Graph:
+    """Stream capture of library calls into one hipGraph.
+
+        with Graph(stream) as g:      # records, runs nothing
+            plan.collide(f, q, stream=stream)
+        g.launch()                    # replays on the same stream
+    """
+
+    def __init__(self, stream=None):
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self._h = None
+
+    def __enter__(self):
+        _lib.check(_lib.lib().fks_graph_begin(_stream_ptr(self.stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        status = _lib.lib().fks_graph_end(_stream_ptr(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            _lib.check(status)
+            self._h = h
+        return False
+
+    def launch(self):
+        _lib.check(_lib.lib().fks_graph_launch(self._h, _stream_ptr(self.stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.fks_graph_destroy(h)
+            self._h = None

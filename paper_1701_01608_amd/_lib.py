@@ -48,6 +48,11 @@ _SIGS = {
     "fks_collide": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fks_relax": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int64, _VP, _VP]),
     "fks_moments": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
+    "fks_heun": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, _VP]),
+    "fks_graph_begin": (ctypes.c_int, [_VP]),
+    "fks_graph_end": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
+    "fks_graph_launch": (ctypes.c_int, [_VP, _VP]),
+    "fks_graph_destroy": (None, [_VP]),
     "fks_collide_grouped": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.POINTER(_VP),
                                            ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64), _VP]),
     "fks_plan_destroy": (None, [_VP]),

@@ -156,6 +156,11 @@ struct fks_plan_s {
   size_t off_fhat = 0, off_scr = 0, off_g = 0, off_d = 0;
 };
 
+struct fks_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct fks_xport_s {
   int n = 0, nx = 0, ny = 0, nz = 0;
   double L = 0.0, dx = 0.0;
@@ -579,7 +584,74 @@ fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const vo
   return ok();
 }
 
+fks_status fks_heun(fks_plan p, void* f, void* f_tmp1, void* f_tmp2, double dt, int32_t n_steps, int64_t n_cells,
+                    void* stream) {
+  fks_status s = check_plan_ready(p);
+  if (s != FKS_OK) return s;
+  if (!std::isfinite(dt)) return fail(FKS_E_ARG, "dt must be finite");
+  if (n_steps < 0 || n_cells < 0) return fail(FKS_E_ARG, "n_steps and n_cells must be >= 0");
+  if (n_steps == 0 || n_cells == 0) return ok();
+  if (!f || !f_tmp1 || !f_tmp2) return fail(FKS_E_ARG, "null buffer");
+  const size_t bytes = size_t(n_cells) * p->n * p->n * p->n * p->esize;
+  if (ranges_overlap(f, f_tmp1, bytes) || ranges_overlap(f, f_tmp2, bytes) || ranges_overlap(f_tmp1, f_tmp2, bytes))
+    return fail(FKS_E_ARG, "f, f_tmp1 and f_tmp2 must not overlap");
+  const int64_t nval = n_cells * int64_t(p->n) * p->n * p->n;
+  for (int st = 0; st < n_steps; ++st) {
+    s = run_collide(p, f, f, nullptr, f_tmp1, dt, n_cells, nullptr, stream);
+    if (s != FKS_OK) return s;
+    s = run_collide(p, f_tmp1, f_tmp1, nullptr, f_tmp2, dt, n_cells, nullptr, stream);
+    if (s != FKS_OK) return s;
+    s = check_hip(fks::launch_average(p->d.dtype == FKS_F32, f, f_tmp2, nval, stream), "heun average");
+    if (s != FKS_OK) return s;
+  }
+  return ok();
+}
+
 void fks_plan_destroy(fks_plan p) { delete p; }
+
+fks_status fks_graph_begin(void* stream) {
+  return check_hip(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal),
+                   "begin capture") == FKS_OK
+             ? ok()
+             : FKS_E_DEVICE;
+}
+
+fks_status fks_graph_end(void* stream, fks_graph* out) {
+  if (!out) return fail(FKS_E_ARG, "null out");
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  fks_status s = check_hip(hipStreamEndCapture(static_cast<hipStream_t>(stream), &g), "end capture");
+  if (s != FKS_OK) return s;
+  hipGraphExec_t e = nullptr;
+  s = check_hip(hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "graph instantiate");
+  if (s != FKS_OK) {
+    hipGraphDestroy(g);
+    return s;
+  }
+  fks_graph_s* h = new (std::nothrow) fks_graph_s();
+  if (!h) {
+    hipGraphExecDestroy(e);
+    hipGraphDestroy(g);
+    return fail(FKS_E_ARG, "out of host memory");
+  }
+  h->graph = g;
+  h->exec = e;
+  *out = h;
+  return ok();
+}
+
+fks_status fks_graph_launch(fks_graph g, void* stream) {
+  if (!g) return fail(FKS_E_ARG, "null graph");
+  return check_hip(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)), "graph launch") == FKS_OK ? ok()
+                                                                                                  : FKS_E_DEVICE;
+}
+
+void fks_graph_destroy(fks_graph g) {
+  if (!g) return;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+}
 
 fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t nz, double dx, fks_xport* out) {
   if (!out) return fail(FKS_E_ARG, "null out");

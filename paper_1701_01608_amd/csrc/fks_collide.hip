@@ -205,20 +205,46 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
         bB[bb] = cpx<T>{T(0), T(0)};
       });
       const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+      // software pipeline over half chunks: the loads of the next half chunk are in
+      // flight while the current one is accumulated
+      constexpr int ZH = (Z + 1) / 2;
+      cpx<T> pf0[ZH], pa0[ZH], pf1[ZH], pa1[ZH];
+      auto load_half = [&](cpx<T>* pf, cpx<T>* pa, int j, auto half) {
+        constexpr int b0 = decltype(half)::value * ZH;
+        const uint32_t s0 = uint32_t(j) * Z * row_bytes;
+        static_for<0, ZH>([&](auto i) {
+          constexpr int bb = b0 + decltype(i)::value;
+          if constexpr (bb < Z) {
+            pf[i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
+            pa[i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
+          }
+        });
+      };
+      auto accumulate = [&](const cpx<T>* pf, const cpx<T>* pa, T cr, T ci, auto half) {
+        constexpr int b0 = decltype(half)::value * ZH;
+        static_for<0, ZH>([&](auto i) {
+          constexpr int bb = b0 + decltype(i)::value;
+          if constexpr (bb < Z) {
+            const cpx<T> fv = pf[i], ab = pa[i];
+            const T ar = ab.re * fv.re, ai = ab.re * fv.im, br = ab.im * fv.re, bi = ab.im * fv.im;
+            const cpx<T> cA = {ar - bi, ai + br};   // (a + ib) fv
+            const cpx<T> cB = {ar + bi, br - ai};   // (a + ib) conj(fv)
+            bA[bb] = bA[bb] + cpx<T>{cr * cA.re - ci * cA.im, cr * cA.im + ci * cA.re};
+            bB[bb] = bB[bb] + cpx<T>{cr * cB.re + ci * cB.im, cr * cB.im - ci * cB.re};
+          }
+        });
+      };
+      using H0 = std::integral_constant<int, 0>;
+      using H1 = std::integral_constant<int, 1>;
+      load_half(pf0, pa0, 0, H0{});
+#pragma unroll 1
       for (int j = 0; j < C::NCH; ++j) {
         const sc wj = chunk_twiddle<C::S>((j * RID) % C::S);
         const T cr = T(wj.c), ci = T(wj.s);
-        const uint32_t s0 = uint32_t(j) * Z * row_bytes;
-        static_for<0, Z>([&](auto bb) {
-          constexpr uint32_t sb = uint32_t(decltype(bb)::value) * row_bytes;
-          const cpx<T> fv = bload2<T>(rf, voff, s0 + sb);
-          const cpx<T> ab = bload2<T>(rt, voff, tterm + s0 + sb);
-          const T ar = ab.re * fv.re, ai = ab.re * fv.im, br = ab.im * fv.re, bi = ab.im * fv.im;
-          const cpx<T> cA = {ar - bi, ai + br};   // (a + ib) fv
-          const cpx<T> cB = {ar + bi, br - ai};   // (a + ib) conj(fv)
-          bA[bb] = bA[bb] + cpx<T>{cr * cA.re - ci * cA.im, cr * cA.im + ci * cA.re};
-          bB[bb] = bB[bb] + cpx<T>{cr * cB.re + ci * cB.im, cr * cB.im - ci * cB.re};
-        });
+        load_half(pf1, pa1, j, H1{});
+        accumulate(pf0, pa0, cr, ci, H0{});
+        if (j + 1 < C::NCH) load_half(pf0, pa0, j + 1, H0{});
+        accumulate(pf1, pa1, cr, ci, H1{});
       }
       // per-bin twiddles and the bin of each partial sum (k_z mod Z, resp. -k_z mod Z)
       cpx<T> oA[Z], oB[Z];
@@ -531,6 +557,26 @@ __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ f, double
     const double w = dv * dv * dv;
     for (int i = 0; i < 5; ++i) u_out[size_t(cell) * 5 + i] = u[i] * w;
   }
+}
+
+// ------------------------------------------------------------------------------------
+// Heun combination f = (f + g)/2
+template <typename T>
+__global__ __launch_bounds__(256) void k_average(T* __restrict__ f, const T* __restrict__ g, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = T(0.5) * (f[i] + g[i]);
+}
+
+hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, void* stream) {
+  const dim3 grid(unsigned((n + 255) / 256));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype_is_f32)
+    hipLaunchKernelGGL(k_average<float>, grid, dim3(256), 0, st, static_cast<float*>(f),
+                       static_cast<const float*>(g), n);
+  else
+    hipLaunchKernelGGL(k_average<double>, grid, dim3(256), 0, st, static_cast<double*>(f),
+                       static_cast<const double*>(g), n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------

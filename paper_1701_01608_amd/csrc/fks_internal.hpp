@@ -55,6 +55,9 @@ hipError_t launch_collide(int dtype_is_f32, int n, const CollideArgs& a);
 hipError_t launch_moments(int dtype_is_f32, int n, const void* f, int64_t cells, double* u, double L,
                           double dv, void* stream);
 
+// f = (f + g) / 2 elementwise over n values
+hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, void* stream);
+
 // transport
 struct XportState {
   double* s;    // [nv][3] sub-cell offsets
