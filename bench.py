@@ -92,6 +92,68 @@ def cpu_baseline(f32_cells, seconds=12.0):
                       f"{wall:.1f} s wall"}
 
 
+def bench_uneven(fks, torch, dev, reps=10):
+    """3000 instances, 1000 each on n = 16, 24, 32 velocity grids (P = 24, 36, 48), hard spheres,
+    M = 12 (3 x 4), FP32, all three groups recorded as one hipGraph and replayed; each group's
+    schedule autotuned.  Inputs: two-Maxwellian mixtures, seeds 1702, 1703, 1704."""
+    import fks_inputs
+    plans, fs, qs = [], [], []
+    for i, n in enumerate((16, 24, 32)):
+        fs.append(torch.tensor(fks_inputs.maxwellian_mixture(n, L, 1000, seed=1702 + i), dtype=torch.float32,
+                               device=dev))
+        qs.append(torch.empty_like(fs[-1]))
+        plans.append(fks.Plan(n, L, R, a1=3, a2=4, C=0.25, dtype="f32", max_cells=1000))
+        plans[-1].autotune(fs[-1], qs[-1])
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with fks.Graph(s) as g:
+            fks.collide_grouped(plans, fs, qs, stream=s)
+        g.launch()
+    s.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(reps):
+            g.launch()
+    s.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    work = 1000 * (16 ** 3 + 24 ** 3 + 32 ** 3)
+    return {"workload": "3000 instances, 1000 each at n=16/24/32, hard spheres M=12, FP32, one hipGraph launch",
+            "ms_per_launch": round(wall * 1e3, 3), "value": round(work / wall, 1), "unit": "sum(n^3)/s",
+            "schedules": [p.schedule() for p in plans]}
+
+
+def bench_fks_step(fks, torch, dev, steps=20):
+    """One GPU's share of the 3D/3D FKS run: 32^3 cells x 32^3 velocities, FP32, periodic box
+    [0,2)^3, f = (1 + 0.1 sin(pi x1)) M_{1,0,1}(v), hard spheres M = 16, dt = 0.004375;
+    each step = exact transport + Euler collision of every cell."""
+    import fks_inputs
+    shape, dx, dt = (32, 32, 32), 2.0 / 32, 0.004375
+    M = fks_inputs.maxwellian_on_grid(N, L, [1.0], [[0.0, 0.0, 0.0]], [1.0])[0]
+    x1 = (np.arange(shape[0]) + 0.5) * dx
+    dens = torch.tensor(1.0 + 0.1 * np.sin(np.pi * x1), dtype=torch.float32, device=dev).reshape(-1, 1, 1, 1, 1, 1)
+    f = (dens * torch.tensor(M, dtype=torch.float32, device=dev).reshape(1, 1, 1, N, N, N)).expand(
+        *shape, N, N, N).contiguous().reshape(-1, N, N, N)
+    cells = f.shape[0]
+    plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=CELLS)
+    xp = fks.Transport(N, L, shape, dx)
+    tmp = torch.empty_like(f)
+    mom = torch.empty((cells, 5), dtype=torch.float64, device=dev)
+    mass0 = float(f.double().sum())
+    fks.step(plan, xp, f, dt, n_steps=1, f_tmp=tmp)     # warm-up step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fks.step(plan, xp, f, dt, n_steps=steps, f_tmp=tmp, moments=mom)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mass = float(mom[:, 0].sum()) / (2.0 * L / N) ** 3      # moments carry dv^3
+    return {"workload": "FKS split steps on 32^3 cells x 32^3 velocities (one GPU's share), FP32, "
+                        "hard spheres M=16, transport + Euler collision", "steps": steps,
+            "ms_per_step": round(wall * 1e3 / steps, 3),
+            "value": round(cells * N ** 3 * steps / wall, 1), "unit": "cells*N^3/s",
+            "box_mass_rel_change": abs(mass - mass0) / mass0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +161,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 32^3-cell FKS step workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -130,6 +193,7 @@ def main():
     f = torch.tensor(f64, dtype=torch.float32, device=dev)
     plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=CELLS)
     q = torch.empty_like(f)
+    schedule = plan.autotune(f, q)      # slab count x XCD mapping, timed on this batch
     for _ in range(args.warmup):
         plan.collide(f, q)
     torch.cuda.synchronize()
@@ -170,7 +234,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch of 4096 cells, hard spheres, n=32, M=16 (4x4), P=48, L=8, R=6, "
                                   "two-Maxwellian mixtures seed 1701", "cells": CELLS, "n": N, "M": M, "P": P},
-           "rel_l2": rel_l2,
+           "rel_l2": rel_l2, "schedule": {"slabs": schedule[0], "xcd_map": schedule[1]},
            "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]},
            "roofline": roofline}
 
@@ -192,6 +256,9 @@ def main():
                            "rel_l2": e64}
         del plan64, fd, qd
 
+    if not args.no_extras:
+        out["uneven_batch"] = bench_uneven(fks, torch, dev)
+        out["fks_step_box"] = bench_fks_step(fks, torch, dev)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -132,6 +132,20 @@ fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const vo
 
 void fks_plan_destroy(fks_plan plan);
 
+/* Slab schedule: each cell's padded convolution grid is split into `slabs` workgroups
+ * (compiled choices per n and dtype), optionally all placed on one XCD (xcd_map = 1).
+ * Results are identical up to rounding order for every schedule. */
+fks_status fks_plan_schedule(fks_plan plan, int32_t* slabs, int32_t* xcd_map);
+fks_status fks_plan_set_schedule(fks_plan plan, int32_t slabs, int32_t xcd_map); /* FKS_E_UNSUPPORTED if not compiled */
+
+/* Autotuner: times every compiled schedule (slab count x XCD mapping) on up to max_cells
+ * cells of f (device, plan dtype; q receives Q) with hipEvents on `stream` (the host waits)
+ * and keeps the fastest.  cache_path (optional, may be NULL): a text file of earlier choices,
+ * one JSON object per line keyed by (device, n, dtype, terms, cells); a matching entry is
+ * used without timing, a new choice is appended. */
+fks_status fks_plan_autotune(fks_plan plan, const void* f, void* q, int64_t n_cells, const char* cache_path,
+                             void* stream);
+
 /* ---- transport (Section 2.1 transport step; Section 3 generic cell) -------------- */
 
 /* Periodic box of nx*ny*nz cells of width dx (cells in C order [nx][ny][nz]) for the
@@ -163,6 +177,68 @@ fks_status fks_step(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double dt
 void fks_xport_destroy(fks_xport xp);
 
 /* ---- stream capture ---------------------------------------------------------------- */
+
+/* ---- Learned surrogate of Q (an extension beyond the paper) ----------------------
+ *
+ * A multilayer perceptron maps the low Fourier modes of a cell's distribution to its
+ * collision operator; cells whose surrogate output fails a conservation check are
+ * recomputed with the spectral operator (Appendix A).  The check uses the moments the
+ * paper's macroscopic variables are built from (Section 3): a correct Q has zero
+ * mass, momentum and energy moments.
+ *
+ * Model: features x = Re, Im of fhat_k / fhat_0 for k in [-m/2, m/2-1]^3 (m = modes),
+ * 2 m^3 values, fhat the normalised Fourier coefficients of f (Appendix A); layers
+ * x -> SiLU(W1 x + b1) -> SiLU(W2 h + b2) -> W3 h + b3 = y (n^3 values); the
+ * prediction is Q = s rho^2 y with rho = (2L)^3 fhat_0 the cell's density and s a
+ * fixed output scale (Q is quadratic in f, so y depends on the shape of f only).  Weights are stored
+ * row-major [out][in]; the host parameter vector is W1, b1, W2, b2, W3, b3 (FP32).
+ * Matrix products run in BF16 on the matrix cores with FP32 accumulation; training
+ * keeps FP32 master weights, Adam moments (beta1 0.9, beta2 0.999, eps 1e-8) and
+ * minimises the mean of (y - t)^2 over batch and outputs.
+ *
+ * Sizes: 2 m^3 and n^3 multiples of 128; width a multiple of 128; batches of
+ * training and fks_sur_forward are multiples of 128 up to max_batch (<= 65536).
+ * Buffers: a parameter buffer (master weights, Adam moments, gradients, BF16
+ * copies) and a workspace (activations), both caller-owned, 256-byte aligned. */
+typedef struct fks_sur_s* fks_sur;
+/* out_scale > 0 fixes the output units: Q = out_scale rho^2 y (choose it near the
+ * typical size of Q / rho^2 so that the network's outputs are of order one). */
+fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_batch, float out_scale,
+                          fks_sur* out);
+/* n_params = number of FP32 values of the host parameter vector */
+fks_status fks_sur_sizes(fks_sur s, size_t* param_bytes, size_t* workspace_bytes, int64_t* n_params);
+fks_status fks_sur_bind(fks_sur s, void* d_params, size_t param_bytes, void* d_workspace, size_t workspace_bytes,
+                        void* stream);
+/* Copies n_params host FP32 values in, resets Adam; synchronises `stream`. */
+fks_status fks_sur_set_params(fks_sur s, const float* host, void* stream);
+/* which = 0: parameters, 1: gradients of the last fks_sur_train_step; n_params host
+ * FP32 values out; synchronises `stream`. */
+fks_status fks_sur_get(fks_sur s, int32_t which, float* host, void* stream);
+/* Features of n_cells distributions f (plan dtype, plan grid n == surrogate n):
+ * x [n_cells][2 m^3] BF16 (device), rho [n_cells] FP32 (device).  Uses the plan's
+ * workspace. */
+fks_status fks_sur_features(fks_sur s, fks_plan plan, const void* f, void* x, float* rho, int64_t n_cells,
+                            void* stream);
+/* Training targets t = q / (s rho^2) ([n_cells][n^3] FP32, device; t may equal q). */
+fks_status fks_sur_targets(fks_sur s, const float* q, const float* rho, float* t, int64_t n_cells, void* stream);
+/* y [batch][n^3] FP32 = network(x), x [batch][2 m^3] BF16, both device. */
+fks_status fks_sur_forward(fks_sur s, const void* x, float* y, int64_t batch, void* stream);
+/* One step on (x, t): forward, loss gradient into the gradient buffer, and, if
+ * `update` != 0, one Adam step with learning rate lr.  t [batch][n^3] FP32 device.
+ * If d_loss != NULL the batch loss (sum of squared errors / (batch n^3), FP64) is
+ * written to device memory d_loss. */
+fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t batch, float lr, int32_t update,
+                              double* d_loss, void* stream);
+/* Q for n_cells FP32 distributions: surrogate prediction, the indicator
+ * r_j = max_i |sum_v phi_i Q_j| / sum_v |phi_i| |Q_j| over phi = 1, v, |v|^2/2 (FP64),
+ * and, for every cell with r_j > threshold (threshold >= 0), the spectral Q of the
+ * FP32 plan `plan` in its place (q = s rho^2 y elsewhere).  threshold < 0 disables the fallback.  Writes the
+ * number of recomputed cells to *n_fallback (host) and, if d_indicator != NULL, r to
+ * d_indicator [n_cells] (device FP64).  Synchronises `stream` once per max_batch
+ * cells (to read the fallback count). */
+fks_status fks_sur_infer(fks_sur s, fks_plan plan, const void* f, float* q, int64_t n_cells, double threshold,
+                         int64_t* n_fallback, double* d_indicator, void* stream);
+void fks_sur_destroy(fks_sur s);
 
 /* Records every library call enqueued on `stream` between fks_graph_begin and
  * fks_graph_end into one hipGraph (no device work runs while recording), so that a

@@ -1,0 +1,129 @@
+"""FP64 reference of the Fourier-mode MLP surrogate (forward, backward, Adam).
+
+Test infrastructure only (see the package header).  Not part of the paper: the learned
+surrogate of the collision operator is an addition of this project; this module is the
+plain reference its GPU training kernels are checked against.
+
+Network: x (features) -> h1 = silu(x W1^T + b1) -> h2 = silu(h1 W2^T + b2) -> y = h2 W3^T + b3,
+weights stored [out][in] (row-major), silu(z) = z sigma(z).
+Loss: mean squared error over all outputs, L = sum (y - t)^2 / (batch * n_out).
+Backward written out by the chain rule:
+    dy = 2 (y - t) / (batch n_out);  dW3 = dy^T h2;  db3 = sum_rows dy;  dh2 = dy W3;
+    dz2 = dh2 silu'(z2);  dW2 = dz2^T h1; ...;  silu'(z) = s (1 + z (1 - s)), s = sigma(z).
+Adam (Kingma & Ba): m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+    p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+"""
+
+import numpy as np
+
+
+def sigmoid(z):
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def silu(z):
+    return z * sigmoid(z)
+
+
+def dsilu(z):
+    s = sigmoid(z)
+    return s * (1.0 + z * (1.0 - s))
+
+
+def init_params(sizes, seed):
+    """He-uniform weights [out][in] and zero biases, drawn with numpy's seeded generator."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for i in range(len(sizes) - 1):
+        fan_in = sizes[i]
+        bound = np.sqrt(6.0 / fan_in)
+        W = rng.uniform(-bound, bound, (sizes[i + 1], sizes[i]))
+        if i == len(sizes) - 2:
+            W *= 0.1      # small output layer
+        params += [W, np.zeros(sizes[i + 1])]
+    return params
+
+
+def forward(params, x):
+    cache = [x]
+    h = x
+    n_layers = len(params) // 2
+    zs = []
+    for i in range(n_layers):
+        W, b = params[2 * i], params[2 * i + 1]
+        z = h @ W.T + b
+        zs.append(z)
+        h = silu(z) if i < n_layers - 1 else z
+        cache.append(h)
+    return h, (cache, zs)
+
+
+def loss_and_grads(params, x, t):
+    y, (cache, zs) = forward(params, x)
+    n = y.size
+    loss = float(np.sum((y - t) ** 2) / n)
+    grads = [None] * len(params)
+    d = 2.0 * (y - t) / n
+    n_layers = len(params) // 2
+    for i in reversed(range(n_layers)):
+        W = params[2 * i]
+        h_in = cache[i]
+        grads[2 * i] = d.T @ h_in
+        grads[2 * i + 1] = d.sum(axis=0)
+        if i > 0:
+            d = (d @ W) * dsilu(zs[i - 1])
+    return loss, grads
+
+
+class Adam:
+    def __init__(self, params, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.m = [np.zeros_like(p) for p in params]
+        self.v = [np.zeros_like(p) for p in params]
+        self.t = 0
+
+    def step(self, params, grads):
+        self.t += 1
+        out = []
+        for p, g, m, v in zip(params, grads, self.m, self.v):
+            m *= self.b1
+            m += (1 - self.b1) * g
+            v *= self.b2
+            v += (1 - self.b2) * g * g
+            mh = m / (1 - self.b1 ** self.t)
+            vh = v / (1 - self.b2 ** self.t)
+            out.append(p - self.lr * mh / (np.sqrt(vh) + self.eps))
+        return out
+
+
+# ---- surrogate inputs and checks -------------------------------------------------------
+def features(f, L, modes):
+    """Network input of one cell: Re, Im (interleaved) of fhat_k / fhat_0 for
+    k in [-modes/2, modes/2 - 1]^3 (k_z fastest), fhat the Appendix A coefficients of
+    the grid samples f (n, n, n); and the density rho = (2L)^3 fhat_0."""
+    from .grid import fourier_coefficients, make_grid
+    n = f.shape[0]
+    g = make_grid(n, L)
+    fh = fourier_coefficients(f, g)
+    c = n // 2 - 1                       # index of k = 0
+    mh = modes // 2
+    sub = fh[c - mh:c + mh, c - mh:c + mh, c - mh:c + mh] / fh[c, c, c]
+    x = np.empty(2 * sub.size)
+    x[0::2] = sub.real.ravel()
+    x[1::2] = sub.imag.ravel()
+    rho = float((2.0 * L) ** 3 * fh[c, c, c].real)
+    return x, rho
+
+
+def moment_indicator(q, L):
+    """max over phi in (1, v_x, v_y, v_z, |v|^2/2) of |sum phi q| / sum |phi| |q| on the
+    velocity grid of q (n, n, n): zero for an operator that conserves mass, momentum and
+    energy (Section 3 macroscopic variables)."""
+    from .grid import make_grid
+    n = q.shape[0]
+    v = make_grid(n, L).v
+    vx, vy, vz = np.meshgrid(v, v, v, indexing="ij")
+    r = 0.0
+    for phi in (np.ones_like(vx), vx, vy, vz, 0.5 * (vx * vx + vy * vy + vz * vz)):
+        r = max(r, abs(np.sum(phi * q)) / np.sum(np.abs(phi) * np.abs(q)))
+    return r

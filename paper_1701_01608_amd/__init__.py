@@ -16,7 +16,7 @@ from ._lib import (FKS_ALLOW_OVERLAP, FKS_CONSERVE, FKS_F32, FKS_F64, FKS_HARD_S
                    FKSError)
 
 __all__ = ["Plan", "Transport", "step", "collide_grouped", "FKSError", "library_path", "profile_start",
-           "profile_stop", "Graph"]
+           "profile_stop", "Graph", "Surrogate"]
 
 _DT = {"f32": (FKS_F32, torch.float32), "f64": (FKS_F64, torch.float64)}
 
@@ -97,6 +97,23 @@ class Plan:
                                         _ptr(moments), _stream_ptr(stream)))
         return f_out
 
+    def schedule(self):
+        sl, xc = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().fks_plan_schedule(self._h, ctypes.byref(sl), ctypes.byref(xc)))
+        return sl.value, xc.value
+
+    def set_schedule(self, slabs, xcd_map=1):
+        _lib.check(_lib.lib().fks_plan_set_schedule(self._h, int(slabs), int(xcd_map)))
+
+    def autotune(self, f, q=None, cache_path=None, stream=None):
+        """Time the compiled slab schedules on f and keep the fastest (optional cache file)."""
+        cells = self._check_f(f)
+        if q is None:
+            q = torch.empty_like(f)
+        path = cache_path.encode() if cache_path else None
+        _lib.check(_lib.lib().fks_plan_autotune(self._h, _ptr(f), _ptr(q), cells, path, _stream_ptr(stream)))
+        return self.schedule()
+
     def heun(self, f, dt, n_steps=1, tmp=None, stream=None):
         """n_steps Heun steps of df/dt = Q(f) in place on f (device scratch tmp: 2 buffers)."""
         cells = self._check_f(f)
@@ -117,6 +134,112 @@ class Plan:
         h = getattr(self, "_h", None)
         if h is not None and _lib._lib is not None:
             _lib._lib.fks_plan_destroy(h)
+            self._h = None
+
+
+class Surrogate:
+    """Fourier-mode MLP surrogate of Q with spectral fallback (fks_sur_* in include/fks.h).
+
+    Parameters, Adam state and activations live in two device buffers allocated here and
+    bound once; every computation runs in the library's kernels."""
+
+    def __init__(self, n, modes=8, width=1024, max_batch=1024, out_scale=1.0, device="cuda", stream=None):
+        L_ = _lib.lib()
+        h = ctypes.c_void_p()
+        _lib.check(L_.fks_sur_create(int(n), int(modes), int(width), int(max_batch), float(out_scale),
+                                     ctypes.byref(h)))
+        self.out_scale = float(out_scale)
+        self._h = h
+        self.n, self.modes, self.width, self.max_batch = int(n), int(modes), int(width), int(max_batch)
+        self.n_in, self.n_out = 2 * self.modes ** 3, self.n ** 3
+        self.device = torch.device(device)
+        pb, wb, npar = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
+        _lib.check(L_.fks_sur_sizes(h, ctypes.byref(pb), ctypes.byref(wb), ctypes.byref(npar)))
+        self.n_params = npar.value
+        self.params_buf = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        _lib.check(L_.fks_sur_bind(h, _ptr(self.params_buf), pb.value, _ptr(self.workspace), wb.value,
+                                   _stream_ptr(stream)))
+        self._loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def shapes(self):
+        w, i, o = self.width, self.n_in, self.n_out
+        return [(w, i), (w,), (w, w), (w,), (o, w), (o,)]
+
+    def set_params(self, params, stream=None):
+        """params: W1, b1, W2, b2, W3, b3 (array-likes, weights [out][in]); resets Adam."""
+        flat = torch.cat([torch.as_tensor(p, dtype=torch.float32).reshape(-1) for p in params]).contiguous()
+        if flat.numel() != self.n_params:
+            raise FKSError(-1, f"expected {self.n_params} parameters, got {flat.numel()}")
+        _lib.check(_lib.lib().fks_sur_set_params(self._h, ctypes.c_void_p(flat.data_ptr()), _stream_ptr(stream)))
+
+    def _get(self, which, stream=None):
+        flat = torch.empty(self.n_params, dtype=torch.float32)
+        _lib.check(_lib.lib().fks_sur_get(self._h, which, ctypes.c_void_p(flat.data_ptr()), _stream_ptr(stream)))
+        out, o = [], 0
+        for shp in self.shapes():
+            k = 1
+            for d in shp:
+                k *= d
+            out.append(flat[o:o + k].reshape(shp).numpy())
+            o += k
+        return out
+
+    def get_params(self, stream=None):
+        return self._get(0, stream)
+
+    def get_grads(self, stream=None):
+        return self._get(1, stream)
+
+    def features(self, plan, f, x=None, rho=None, stream=None):
+        cells = plan._check_f(f)
+        if x is None:
+            x = torch.empty((cells, self.n_in), dtype=torch.bfloat16, device=f.device)
+        if rho is None:
+            rho = torch.empty(cells, dtype=torch.float32, device=f.device)
+        if not (x.dtype == torch.bfloat16 and x.is_contiguous() and x.numel() >= cells * self.n_in):
+            raise FKSError(-1, "x must be a contiguous bfloat16 tensor of [cells, 2 modes^3]")
+        _lib.check(_lib.lib().fks_sur_features(self._h, plan.handle, _ptr(f), _ptr(x), _ptr(rho), cells,
+                                               _stream_ptr(stream)))
+        return x, rho
+
+    def targets(self, q, rho, t=None, stream=None):
+        cells = q.numel() // self.n_out
+        if t is None:
+            t = torch.empty_like(q)
+        _lib.check(_lib.lib().fks_sur_targets(self._h, _ptr(q), _ptr(rho), _ptr(t), cells, _stream_ptr(stream)))
+        return t
+
+    def forward(self, x, y=None, stream=None):
+        batch = x.shape[0]
+        if y is None:
+            y = torch.empty((batch, self.n_out), dtype=torch.float32, device=x.device)
+        _lib.check(_lib.lib().fks_sur_forward(self._h, _ptr(x), _ptr(y), batch, _stream_ptr(stream)))
+        return y
+
+    def train_step(self, x, t, lr, update=True, loss=None, stream=None):
+        """One forward/backward (and Adam step if update); returns the device loss tensor."""
+        batch = x.shape[0]
+        loss = self._loss if loss is None else loss
+        _lib.check(_lib.lib().fks_sur_train_step(self._h, _ptr(x), _ptr(t), batch, float(lr), int(bool(update)),
+                                                 _ptr(loss), _stream_ptr(stream)))
+        return loss
+
+    def infer(self, plan, f, q=None, threshold=1e-3, indicator=None, stream=None):
+        """Q of FP32 cells f: surrogate, indicator, spectral fallback where it exceeds
+        threshold (threshold < 0: none).  Returns (q, number of fallback cells)."""
+        cells = plan._check_f(f)
+        if q is None:
+            q = torch.empty_like(f)
+        nf = ctypes.c_int64()
+        _lib.check(_lib.lib().fks_sur_infer(self._h, plan.handle, _ptr(f), _ptr(q), cells, float(threshold),
+                                            ctypes.byref(nf), _ptr(indicator), _stream_ptr(stream)))
+        return q, nf.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.fks_sur_destroy(h)
             self._h = None
 
 

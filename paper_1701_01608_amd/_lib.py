@@ -56,6 +56,9 @@ _SIGS = {
     "fks_collide_grouped": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.POINTER(_VP),
                                            ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64), _VP]),
     "fks_plan_destroy": (None, [_VP]),
+    "fks_plan_schedule": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "fks_plan_set_schedule": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "fks_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_char_p, _VP]),
     "fks_xport_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_VP)]),
     "fks_xport_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
@@ -63,6 +66,21 @@ _SIGS = {
     "fks_transport": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_double, _VP]),
     "fks_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, _VP, _VP]),
     "fks_xport_destroy": (None, [_VP]),
+    "fks_sur_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_float, ctypes.POINTER(_VP)]),
+    "fks_sur_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "fks_sur_bind": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.c_size_t, _VP]),
+    "fks_sur_set_params": (ctypes.c_int, [_VP, _VP, _VP]),
+    "fks_sur_get": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "fks_sur_features": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_sur_targets": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_sur_forward": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_sur_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _VP,
+                                          _VP]),
+    "fks_sur_infer": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_int64), _VP, _VP]),
+    "fks_sur_destroy": (None, [_VP]),
     "fks_profile_start": (ctypes.c_int, []),
     "fks_profile_stop": (ctypes.c_int, [ctypes.POINTER(ProfileStats)]),
     "fks_last_error": (ctypes.c_char_p, []),

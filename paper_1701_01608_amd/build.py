@@ -32,6 +32,7 @@ EXACT_FLAGS = ["-ffp-contract=off"]
 SOURCES = [
     ("fks_collide.hip", FFT_FLAGS),
     ("fks_transport.hip", EXACT_FLAGS),
+    ("fks_surrogate.hip", ["-fno-math-errno"]),
     ("fks_api.cpp", EXACT_FLAGS),
 ]
 

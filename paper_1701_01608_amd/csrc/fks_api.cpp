@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -154,6 +155,31 @@ struct fks_plan_s {
   bool bound = false;
   // workspace carve-up (byte offsets)
   size_t off_fhat = 0, off_scr = 0, off_g = 0, off_d = 0;
+  // slab schedule (index into geo.variant_slabs) and workgroup-to-XCD mapping
+  int variant = 0;
+  int xcd_map = 1;
+};
+
+// Surrogate: FP32 master parameters, Adam moments, gradients and BF16 weight copies in
+// the caller's parameter buffer; activations in the caller's workspace.
+struct fks_sur_s {
+  int n = 0, modes = 0, width = 0;
+  float scale = 1.0f;  // Q = scale * rho^2 * y
+  int64_t max_batch = 0;
+  int fin = 0, fout = 0;  // features 2*modes^3, outputs n^3
+  size_t n_params = 0;
+  size_t off_w[3] = {}, off_b[3] = {};  // element offsets into one FP32 tensor
+  void* d_params = nullptr;
+  void* d_ws = nullptr;
+  size_t param_bytes = 0, ws_bytes = 0;
+  // parameter buffer carve-up (bytes)
+  size_t p_master = 0, p_m = 0, p_v = 0, p_g = 0, p_w16 = 0;
+  // workspace carve-up (bytes)
+  size_t w_z1 = 0, w_z2 = 0, w_h1 = 0, w_h2 = 0, w_y = 0, w_dy = 0, w_dz1 = 0, w_dz2 = 0, w_part = 0, w_rho = 0,
+         w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0;
+  int part_blocks = 256;
+  int64_t adam_t = 0;
+  bool bound = false;
 };
 
 struct fks_graph_s {
@@ -354,6 +380,8 @@ fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, 
     a.moments = moments ? moments + size_t(c0) * 5 : nullptr;
     a.ep = p->ep;
     a.stream = stream;
+    a.variant = p->variant;
+    a.xcd_map = p->xcd_map;
     const fks_status s = check_hip(fks::launch_collide(f32, p->n, a), "collide launch");
     if (s != FKS_OK) return s;
   }
@@ -608,6 +636,442 @@ fks_status fks_heun(fks_plan p, void* f, void* f_tmp1, void* f_tmp2, double dt, 
 }
 
 void fks_plan_destroy(fks_plan p) { delete p; }
+
+fks_status fks_plan_schedule(fks_plan p, int32_t* slabs, int32_t* xcd_map) {
+  if (!p || !slabs || !xcd_map) return fail(FKS_E_ARG, "null argument");
+  *slabs = p->geo.variant_slabs[p->variant];
+  *xcd_map = p->xcd_map;
+  return ok();
+}
+
+fks_status fks_plan_set_schedule(fks_plan p, int32_t slabs, int32_t xcd_map) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  for (int v = 0; v < p->geo.n_variants; ++v)
+    if (p->geo.variant_slabs[v] == slabs) {
+      p->variant = v;
+      p->xcd_map = xcd_map ? 1 : 0;
+      return ok();
+    }
+  return fail(FKS_E_UNSUPPORTED, "no compiled schedule with %d slabs for n = %d", slabs, p->n);
+}
+
+namespace {
+std::string device_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// cache line: {"device":"gfx950","n":32,"dtype":"f32","terms":17,"cells":4096,"slabs":6,"xcd":1,"ms":15.0}
+bool cache_lookup(const char* path, const std::string& key, int* slabs, int* xcd) {
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), fp)) {
+    const std::string l(line);
+    if (l.find(key) == std::string::npos) continue;
+    const size_t ps = l.find("\"slabs\":"), px = l.find("\"xcd\":");
+    if (ps == std::string::npos || px == std::string::npos) continue;
+    *slabs = std::atoi(l.c_str() + ps + 8);
+    *xcd = std::atoi(l.c_str() + px + 6);
+    found = true;  // the last matching line wins
+  }
+  std::fclose(fp);
+  return found;
+}
+}  // namespace
+
+fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells, const char* cache_path,
+                             void* stream) {
+  fks_status s = check_plan_ready(p);
+  if (s != FKS_OK) return s;
+  if (!f || !q || n_cells < 1) return fail(FKS_E_ARG, "need f, q and n_cells >= 1");
+  if (n_cells > p->max_cells) n_cells = p->max_cells;
+  char keybuf[256];
+  std::snprintf(keybuf, sizeof(keybuf), "\"device\":\"%s\",\"n\":%d,\"dtype\":\"%s\",\"terms\":%d,\"cells\":%lld",
+                device_name().c_str(), p->n, p->d.dtype == FKS_F32 ? "f32" : "f64", p->n_terms,
+                static_cast<long long>(n_cells));
+  const std::string key(keybuf);
+  int cs = 0, cx = 0;
+  if (cache_path && cache_lookup(cache_path, key, &cs, &cx) && fks_plan_set_schedule(p, cs, cx) == FKS_OK)
+    return ok();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  s = check_hip(hipEventCreate(&e0), "event");
+  if (s != FKS_OK) return s;
+  s = check_hip(hipEventCreate(&e1), "event");
+  if (s != FKS_OK) {
+    hipEventDestroy(e0);
+    return s;
+  }
+  float best = 1e30f;
+  int best_v = p->variant, best_x = p->xcd_map;
+  for (int v = 0; v < p->geo.n_variants && s == FKS_OK; ++v)
+    for (int x = 0; x < 2 && s == FKS_OK; ++x) {
+      p->variant = v;
+      p->xcd_map = x;
+      s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);  // warm-up
+      if (s != FKS_OK) break;
+      s = check_hip(hipEventRecord(e0, st), "event record");
+      for (int r = 0; r < 3 && s == FKS_OK; ++r) s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
+      if (s == FKS_OK) s = check_hip(hipEventRecord(e1, st), "event record");
+      if (s == FKS_OK) s = check_hip(hipEventSynchronize(e1), "event sync");
+      float ms = 0.f;
+      if (s == FKS_OK) s = check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      if (s == FKS_OK && ms < best) {
+        best = ms;
+        best_v = v;
+        best_x = x;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  p->variant = best_v;
+  p->xcd_map = best_x;
+  if (s != FKS_OK) return s;
+  if (cache_path) {
+    FILE* fp = std::fopen(cache_path, "a");
+    if (fp) {
+      std::fprintf(fp, "{%s,\"slabs\":%d,\"xcd\":%d,\"ms\":%.4f}\n", key.c_str(), p->geo.variant_slabs[best_v], best_x,
+                   best / 3.0f);
+      std::fclose(fp);
+    }
+  }
+  return ok();
+}
+
+// ---- surrogate ----------------------------------------------------------------------
+namespace {
+unsigned char* B(void* p, size_t off) { return static_cast<unsigned char*>(p) + off; }
+
+// FP32 -> BF16 with round to nearest even (the rounding the device conversion uses)
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+fks_status sur_ready(const fks_sur_s* s) {
+  if (!s) return fail(FKS_E_ARG, "null surrogate");
+  if (!s->bound) return fail(FKS_E_STATE, "surrogate buffers not bound (call fks_sur_bind)");
+  return FKS_OK;
+}
+
+// forward pass of a batch (rows multiple of 128) into Z1, H1, Z2, H2 and Y
+fks_status sur_forward(fks_sur_s* s, const void* x, int64_t rows, void* stream) {
+  const float* P = reinterpret_cast<const float*>(B(s->d_params, s->p_master));
+  const unsigned char* W16 = B(s->d_params, s->p_w16);
+  const int w = s->width, fi = s->fin, fo = s->fout, r = int(rows);
+  fks_status st = check_hip(fks::launch_gemm(0, 0, fks::kEpiBiasSilu_, x, W16 + 2 * s->off_w[0], r, w, fi, fi, fi,
+                                             P + s->off_b[0], reinterpret_cast<float*>(B(s->d_ws, s->w_z1)),
+                                             B(s->d_ws, s->w_h1), nullptr, w, stream),
+                            "surrogate layer 1");
+  if (st != FKS_OK) return st;
+  st = check_hip(fks::launch_gemm(0, 0, fks::kEpiBiasSilu_, B(s->d_ws, s->w_h1), W16 + 2 * s->off_w[1], r, w, w, w, w,
+                                  P + s->off_b[1], reinterpret_cast<float*>(B(s->d_ws, s->w_z2)), B(s->d_ws, s->w_h2),
+                                  nullptr, w, stream),
+                 "surrogate layer 2");
+  if (st != FKS_OK) return st;
+  return check_hip(fks::launch_gemm(0, 0, fks::kEpiF32_, B(s->d_ws, s->w_h2), W16 + 2 * s->off_w[2], r, fo, w, w, w,
+                                    P + s->off_b[2], reinterpret_cast<float*>(B(s->d_ws, s->w_y)), nullptr, nullptr,
+                                    fo, stream),
+                   "surrogate layer 3");
+}
+
+// gradients of the MSE of the batch against targets t into the gradient buffer
+fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t rows, double* d_loss, void* stream) {
+  float* G = reinterpret_cast<float*>(B(s->d_params, s->p_g));
+  const unsigned char* W16 = B(s->d_params, s->p_w16);
+  const int w = s->width, fi = s->fin, fo = s->fout, r = int(rows);
+  void* dy = B(s->d_ws, s->w_dy);
+  double* part = reinterpret_cast<double*>(B(s->d_ws, s->w_part));
+  fks_status st = check_hip(fks::launch_mse(reinterpret_cast<const float*>(B(s->d_ws, s->w_y)), t, dy,
+                                            int64_t(r) * fo, part, s->part_blocks, stream),
+                            "surrogate loss");
+  if (st != FKS_OK) return st;
+  if (d_loss) {
+    st = check_hip(fks::launch_sum_partials(part, s->part_blocks, d_loss, stream), "loss sum");
+    if (st != FKS_OK) return st;
+  }
+  // layer 3: dW3 = dY^T H2, db3 = colsum dY, dZ2 = (dY W3) silu'(Z2)
+  st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, dy, B(s->d_ws, s->w_h2), fo, w, r, fo, w, nullptr,
+                                  G + s->off_w[2], nullptr, nullptr, w, stream),
+                 "dW3");
+  if (st == FKS_OK) st = check_hip(fks::launch_colsum(dy, r, fo, G + s->off_b[2], stream), "db3");
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_gemm(0, 1, fks::kEpiDSilu_, dy, W16 + 2 * s->off_w[2], r, w, fo, fo, w, nullptr,
+                                    nullptr, B(s->d_ws, s->w_dz2),
+                                    reinterpret_cast<const float*>(B(s->d_ws, s->w_z2)), w, stream),
+                   "dZ2");
+  // layer 2
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz2), B(s->d_ws, s->w_h1), w, w, r, w, w,
+                                    nullptr, G + s->off_w[1], nullptr, nullptr, w, stream),
+                   "dW2");
+  if (st == FKS_OK) st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz2), r, w, G + s->off_b[1], stream), "db2");
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_gemm(0, 1, fks::kEpiDSilu_, B(s->d_ws, s->w_dz2), W16 + 2 * s->off_w[1], r, w, w, w, w,
+                                    nullptr, nullptr, B(s->d_ws, s->w_dz1),
+                                    reinterpret_cast<const float*>(B(s->d_ws, s->w_z1)), w, stream),
+                   "dZ1");
+  // layer 1
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz1), x, w, fi, r, w, fi, nullptr,
+                                    G + s->off_w[0], nullptr, nullptr, fi, stream),
+                   "dW1");
+  if (st == FKS_OK) st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz1), r, w, G + s->off_b[0], stream), "db1");
+  return st;
+}
+}  // namespace
+
+fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_batch, float out_scale, fks_sur* out) {
+  if (!out) return fail(FKS_E_ARG, "null out");
+  *out = nullptr;
+  if (!(out_scale > 0.0f) || !std::isfinite(out_scale)) return fail(FKS_E_ARG, "out_scale must be positive");
+  if (n < 4 || n > 64) return fail(FKS_E_ARG, "n out of range");
+  if (modes < 2 || modes % 2 || modes > n - 2) return fail(FKS_E_ARG, "modes must be even and <= n - 2");
+  const int64_t fin = 2 * int64_t(modes) * modes * modes, fout = int64_t(n) * n * n;
+  if (fin % 128 || fout % 128) return fail(FKS_E_UNSUPPORTED, "2*modes^3 and n^3 must be multiples of 128");
+  if (width < 128 || width % 128) return fail(FKS_E_ARG, "width must be a positive multiple of 128");
+  if (max_batch < 128 || max_batch % 128 || max_batch > (int64_t(1) << 16))
+    return fail(FKS_E_ARG, "max_batch must be a multiple of 128 in [128, 65536]");
+  fks_sur_s* s = new (std::nothrow) fks_sur_s();
+  if (!s) return fail(FKS_E_ARG, "out of host memory");
+  s->n = n;
+  s->scale = out_scale;
+  s->modes = modes;
+  s->width = width;
+  s->max_batch = max_batch;
+  s->fin = int(fin);
+  s->fout = int(fout);
+  const size_t w = size_t(width), fi = size_t(fin), fo = size_t(fout);
+  size_t o = 0;
+  s->off_w[0] = o;  o += w * fi;
+  s->off_b[0] = o;  o += w;
+  s->off_w[1] = o;  o += w * w;
+  s->off_b[1] = o;  o += w;
+  s->off_w[2] = o;  o += fo * w;
+  s->off_b[2] = o;  o += fo;
+  s->n_params = o;
+  size_t pb = 0;
+  s->p_master = pb;  pb = round256(pb + 4 * o);
+  s->p_m = pb;       pb = round256(pb + 4 * o);
+  s->p_v = pb;       pb = round256(pb + 4 * o);
+  s->p_g = pb;       pb = round256(pb + 4 * o);
+  s->p_w16 = pb;     pb = round256(pb + 2 * o);  // same element offsets (biases unused)
+  s->param_bytes = pb;
+  const size_t Bm = size_t(max_batch);
+  size_t wb = 0;
+  s->w_z1 = wb;   wb = round256(wb + 4 * Bm * w);
+  s->w_z2 = wb;   wb = round256(wb + 4 * Bm * w);
+  s->w_h1 = wb;   wb = round256(wb + 2 * Bm * w);
+  s->w_h2 = wb;   wb = round256(wb + 2 * Bm * w);
+  s->w_y = wb;    wb = round256(wb + 4 * Bm * fo);
+  s->w_dy = wb;   wb = round256(wb + 2 * Bm * fo);
+  s->w_dz1 = wb;  wb = round256(wb + 2 * Bm * w);
+  s->w_dz2 = wb;  wb = round256(wb + 2 * Bm * w);
+  s->w_part = wb; wb = round256(wb + 8 * size_t(s->part_blocks));
+  s->w_rho = wb;  wb = round256(wb + 4 * Bm);
+  s->w_r = wb;    wb = round256(wb + 8 * Bm);
+  s->w_list = wb; wb = round256(wb + 4 * Bm);
+  s->w_cnt = wb;  wb = round256(wb + 4);
+  s->w_x = wb;    wb = round256(wb + 2 * Bm * fi);
+  s->w_gf = wb;   wb = round256(wb + 4 * Bm * fo);  // fallback gather buffers (FP32 cells)
+  s->w_gq = wb;   wb = round256(wb + 4 * Bm * fo);
+  s->ws_bytes = wb;
+  *out = s;
+  return ok();
+}
+
+fks_status fks_sur_sizes(fks_sur s, size_t* param_bytes, size_t* workspace_bytes, int64_t* n_params) {
+  if (!s || !param_bytes || !workspace_bytes || !n_params) return fail(FKS_E_ARG, "null argument");
+  *param_bytes = s->param_bytes;
+  *workspace_bytes = s->ws_bytes;
+  *n_params = int64_t(s->n_params);
+  return ok();
+}
+
+fks_status fks_sur_bind(fks_sur s, void* d_params, size_t param_bytes, void* d_workspace, size_t workspace_bytes,
+                        void* stream) {
+  (void)stream;
+  if (!s || !d_params || !d_workspace) return fail(FKS_E_ARG, "null argument");
+  if (!aligned(d_params) || !aligned(d_workspace)) return fail(FKS_E_ARG, "buffers must be 256-byte aligned");
+  if (param_bytes < s->param_bytes || workspace_bytes < s->ws_bytes) return fail(FKS_E_WORKSPACE, "buffers too small");
+  s->d_params = d_params;
+  s->d_ws = d_workspace;
+  s->bound = true;
+  return ok();
+}
+
+fks_status fks_sur_set_params(fks_sur s, const float* host, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  if (!host) return fail(FKS_E_ARG, "null params");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  std::vector<uint16_t> h16(s->n_params);
+  for (size_t i = 0; i < s->n_params; ++i) h16[i] = bf16_bits(host[i]);
+  st = check_hip(hipMemcpyAsync(B(s->d_params, s->p_master), host, 4 * s->n_params, hipMemcpyHostToDevice, hs), "params");
+  if (st == FKS_OK)
+    st = check_hip(hipMemcpyAsync(B(s->d_params, s->p_w16), h16.data(), 2 * s->n_params, hipMemcpyHostToDevice, hs),
+                   "params16");
+  std::vector<float> zeros(s->n_params, 0.0f);
+  if (st == FKS_OK)
+    st = check_hip(hipMemcpyAsync(B(s->d_params, s->p_m), zeros.data(), 4 * s->n_params, hipMemcpyHostToDevice, hs), "m");
+  if (st == FKS_OK)
+    st = check_hip(hipMemcpyAsync(B(s->d_params, s->p_v), zeros.data(), 4 * s->n_params, hipMemcpyHostToDevice, hs), "v");
+  if (st == FKS_OK) st = check_hip(hipStreamSynchronize(hs), "params sync");  // host vectors go out of scope
+  s->adam_t = 0;
+  return st == FKS_OK ? ok() : st;
+}
+
+fks_status fks_sur_get(fks_sur s, int32_t which, float* host, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  if (!host || which < 0 || which > 1) return fail(FKS_E_ARG, "bad arguments");
+  const size_t off = which == 0 ? s->p_master : s->p_g;
+  st = check_hip(hipMemcpyAsync(host, B(s->d_params, off), 4 * s->n_params, hipMemcpyDeviceToHost,
+                                static_cast<hipStream_t>(stream)),
+                 "copy out");
+  if (st == FKS_OK) st = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sync");
+  return st == FKS_OK ? ok() : st;
+}
+
+fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float* rho, int64_t n_cells, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  st = check_plan_ready(p);
+  if (st != FKS_OK) return st;
+  if (p->n != s->n) return fail(FKS_E_ARG, "plan and surrogate grids differ");
+  if (n_cells < 0 || (n_cells > 0 && (!f || !x || !rho))) return fail(FKS_E_ARG, "bad buffers");
+  const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
+  const int f32 = p->d.dtype == FKS_F32;
+  const double box3 = 8.0 * p->d.L * p->d.L * p->d.L;
+  unsigned char* ws = static_cast<unsigned char*>(p->d_ws);
+  for (int64_t c0 = 0; c0 < n_cells; c0 += p->max_cells) {
+    const int64_t c = (n_cells - c0 < p->max_cells) ? (n_cells - c0) : p->max_cells;
+    st = check_hip(fks::launch_forward(f32, p->n, static_cast<const unsigned char*>(f) + size_t(c0) * cell_bytes,
+                                       ws + p->off_fhat, ws + p->off_scr, c, stream),
+                   "feature transform");
+    if (st != FKS_OK) return st;
+    st = check_hip(fks::launch_lowmodes(f32, ws + p->off_fhat, p->geo.table_rows, p->n / 2, p->geo.npair, p->K, p->Kh,
+                                        s->modes / 2, box3, static_cast<unsigned char*>(x) + size_t(c0) * 2 * s->fin,
+                                        s->fin, rho + c0, c, stream),
+                   "low modes");
+    if (st != FKS_OK) return st;
+  }
+  return ok();
+}
+
+fks_status fks_sur_targets(fks_sur s, const float* q, const float* rho, float* t, int64_t n_cells, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  if (n_cells < 0 || (n_cells > 0 && (!q || !rho || !t))) return fail(FKS_E_ARG, "bad buffers");
+  if (n_cells == 0) return ok();
+  if (n_cells > (int64_t(1) << 31) - 1) return fail(FKS_E_ARG, "too many cells");
+  return check_hip(fks::launch_sur_target(q, rho, 1.0f / s->scale, t, s->fout, n_cells, stream), "targets") == FKS_OK ? ok()
+                                                                                                  : FKS_E_DEVICE;
+}
+
+fks_status fks_sur_forward(fks_sur s, const void* x, float* y, int64_t batch, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  if (!x || !y || batch < 128 || batch % 128 || batch > s->max_batch)
+    return fail(FKS_E_ARG, "batch must be a multiple of 128 up to max_batch");
+  st = sur_forward(s, x, batch, stream);
+  if (st != FKS_OK) return st;
+  return check_hip(hipMemcpyAsync(y, B(s->d_ws, s->w_y), size_t(4) * batch * s->fout, hipMemcpyDeviceToDevice,
+                                  static_cast<hipStream_t>(stream)),
+                   "copy y") == FKS_OK
+             ? ok()
+             : FKS_E_DEVICE;
+}
+
+fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t batch, float lr, int32_t update,
+                              double* d_loss, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  if (!x || !t || batch < 128 || batch % 128 || batch > s->max_batch)
+    return fail(FKS_E_ARG, "batch must be a multiple of 128 up to max_batch");
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(FKS_E_ARG, "bad learning rate");
+  st = sur_forward(s, x, batch, stream);
+  if (st == FKS_OK) st = sur_backward(s, x, t, batch, d_loss, stream);
+  if (st != FKS_OK || !update) return st == FKS_OK ? ok() : st;
+  s->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = float(1.0 - std::pow(0.9, double(s->adam_t))), c2 = float(1.0 - std::pow(0.999, double(s->adam_t)));
+  float* P = reinterpret_cast<float*>(B(s->d_params, s->p_master));
+  float* M = reinterpret_cast<float*>(B(s->d_params, s->p_m));
+  float* V = reinterpret_cast<float*>(B(s->d_params, s->p_v));
+  float* G = reinterpret_cast<float*>(B(s->d_params, s->p_g));
+  unsigned char* W16 = B(s->d_params, s->p_w16);
+  for (int l = 0; l < 3 && st == FKS_OK; ++l) {
+    const size_t nw = s->off_b[l] - s->off_w[l];
+    const size_t nb = (l < 2 ? s->off_w[l + 1] : s->n_params) - s->off_b[l];
+    st = check_hip(fks::launch_adam(P + s->off_w[l], M + s->off_w[l], V + s->off_w[l], G + s->off_w[l],
+                                    W16 + 2 * s->off_w[l], int64_t(nw), lr, b1, b2, eps, c1, c2, stream),
+                   "adam W");
+    if (st == FKS_OK)
+      st = check_hip(fks::launch_adam(P + s->off_b[l], M + s->off_b[l], V + s->off_b[l], G + s->off_b[l], nullptr,
+                                      int64_t(nb), lr, b1, b2, eps, c1, c2, stream),
+                     "adam b");
+  }
+  return st == FKS_OK ? ok() : st;
+}
+
+fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t n_cells, double threshold,
+                         int64_t* n_fallback, double* d_indicator, void* stream) {
+  fks_status st = sur_ready(s);
+  if (st != FKS_OK) return st;
+  st = check_plan_ready(p);
+  if (st != FKS_OK) return st;
+  if (p->n != s->n || p->d.dtype != FKS_F32) return fail(FKS_E_ARG, "fallback plan must be FP32 on the same grid");
+  if (n_cells < 0 || (n_cells > 0 && (!f || !q))) return fail(FKS_E_ARG, "bad buffers");
+  if (n_fallback) *n_fallback = 0;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int n3 = s->fout;
+  const size_t cell_bytes = size_t(n3) * 4;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += s->max_batch) {
+    const int64_t c = (n_cells - c0 < s->max_batch) ? (n_cells - c0) : s->max_batch;
+    const int64_t rows = (c + 127) / 128 * 128;
+    const unsigned char* fc = static_cast<const unsigned char*>(f) + size_t(c0) * cell_bytes;
+    float* qc = q + size_t(c0) * n3;
+    float* rho = reinterpret_cast<float*>(B(s->d_ws, s->w_rho));
+    double* r = d_indicator ? d_indicator + c0 : reinterpret_cast<double*>(B(s->d_ws, s->w_r));
+    st = fks_sur_features(s, p, fc, B(s->d_ws, s->w_x), rho, c, stream);
+    if (st == FKS_OK) st = sur_forward(s, B(s->d_ws, s->w_x), rows, stream);
+    if (st == FKS_OK)
+      st = check_hip(fks::launch_sur_output(reinterpret_cast<const float*>(B(s->d_ws, s->w_y)), n3, rho, s->scale, s->n,
+                                            p->d.L, qc, r, c, stream),
+                     "surrogate output");
+    if (st != FKS_OK) return st;
+    if (!(threshold >= 0.0)) continue;  // negative threshold: no fallback
+    int* list = reinterpret_cast<int*>(B(s->d_ws, s->w_list));
+    int* cnt = reinterpret_cast<int*>(B(s->d_ws, s->w_cnt));
+    st = check_hip(fks::launch_compact(r, int(c), threshold, list, cnt, stream), "compact");
+    int h_cnt = 0;
+    if (st == FKS_OK) st = check_hip(hipMemcpyAsync(&h_cnt, cnt, 4, hipMemcpyDeviceToHost, hs), "count");
+    if (st == FKS_OK) st = check_hip(hipStreamSynchronize(hs), "count sync");
+    if (st != FKS_OK) return st;
+    if (h_cnt > 0) {
+      float* gf = reinterpret_cast<float*>(B(s->d_ws, s->w_gf));
+      float* gq = reinterpret_cast<float*>(B(s->d_ws, s->w_gq));
+      st = check_hip(fks::launch_gather_cells(0, reinterpret_cast<const float*>(fc), gf, list, h_cnt, n3, stream), "gather");
+      if (st == FKS_OK) st = run_collide(p, gf, nullptr, gq, nullptr, 0.0, h_cnt, nullptr, stream);
+      if (st == FKS_OK) st = check_hip(fks::launch_gather_cells(1, gq, qc, list, h_cnt, n3, stream), "scatter");
+      if (st != FKS_OK) return st;
+    }
+    if (n_fallback) *n_fallback += h_cnt;
+  }
+  return ok();
+}
+
+void fks_sur_destroy(fks_sur s) { delete s; }
 
 fks_status fks_graph_begin(void* stream) {
   return check_hip(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal),

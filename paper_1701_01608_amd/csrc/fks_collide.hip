@@ -26,28 +26,50 @@
 
 namespace fks {
 
-// Slab decomposition per (precision, n).  FP32: S slabs of Z planes so that
-// 2*Z*P <= 1024 threads each own half an x line (P/2 values, x of one parity) of the
-// slab accumulator G in registers; the LDS holds the stage buffer [Z][n-1][P+1]
-// complex.  FP64: G lives in a per-slab workspace region and 256 threads loop over
-// whole lines.
+// Compiled slab schedules per (precision, n): the number of slabs S per cell (the
+// autotuner picks one at run time).  FP32: each of 2*Z*P <= 1024 threads owns half an x
+// line (P/2 values of one parity) of the slab accumulator G in registers; FP64: G lives in
+// a per-slab workspace region and 256 threads loop over whole lines.
 template <typename T, int N>
-struct Cfg {
+struct Variants;
+template <int N>
+struct Variants<float, N> {
+  static constexpr int count = (N >= 16) ? 2 : 1;
+  static constexpr int s[2] = {N >= 24 ? 6 : (N >= 16 ? 3 : 1), N >= 32 ? 8 : (N >= 24 ? 9 : 6)};
+};
+template <int N>
+struct Variants<double, N> {
+  static constexpr int count = 1;
+  static constexpr int s[2] = {N >= 32 ? 8 : (N >= 24 ? 4 : 1), 0};
+};
+
+// Grid constants shared by all schedules of (precision, n).
+template <typename T, int N>
+struct Grid {
   static constexpr int P = 3 * N / 2;
   static constexpr int K = N - 1;
   static constexpr int Kh = N / 2 - 1;
   static constexpr int KH1 = Kh + 1;
   static constexpr int WS = P + 1;
   static constexpr int NPAIR = (K * K + 1) / 2;  // z pencils (kx, ky) of the half plane
+  static constexpr int rows_for(int S) { return ((N + (P / S) - 1) / (P / S)) * (P / S); }
+  // fhat / table layout rows: k_z = row - N/2; row 0 (the dropped Nyquist mode) and rows
+  // >= N are zero; enough rows for the chunking of every compiled schedule
+  static constexpr int NRL = rows_for(Variants<T, N>::s[0]) > (Variants<T, N>::count > 1 ? rows_for(Variants<T, N>::s[1]) : 0)
+                                 ? rows_for(Variants<T, N>::s[0])
+                                 : rows_for(Variants<T, N>::s[1]);
+};
+
+template <typename T, int N, int S_>
+struct Cfg : Grid<T, N> {
+  using G_ = Grid<T, N>;
+  static constexpr int P = G_::P, K = G_::K, Kh = G_::Kh, KH1 = G_::KH1, WS = G_::WS, NPAIR = G_::NPAIR;
+  static constexpr int NRL = G_::NRL;
   static constexpr bool GREG = sizeof(T) == 4;
-  static constexpr int S = GREG ? (N >= 24 ? 6 : (N >= 16 ? 3 : 1))
-                                : (N >= 32 ? 8 : (N >= 24 ? 4 : 1));
+  static constexpr int S = S_;
   static constexpr int Z = P / S;
   static constexpr int LINES = Z * P;  // x lines (z', y) of the slab
-  // fhat / table rows: k_z = row - N/2, rows grouped in NCH chunks of Z (the fold period);
-  // row 0 (the dropped Nyquist mode) and rows >= N are zero
-  static constexpr int NCH = (N + Z - 1) / Z;
-  static constexpr int NR = NCH * Z;
+  static constexpr int NCH = (N + Z - 1) / Z;  // k_z chunks of the fold period Z
   static constexpr int NT = GREG ? ((2 * LINES + 63) / 64) * 64 : 256;
   static constexpr size_t w_bytes = size_t(Z) * K * WS * sizeof(cpx<T>);
   // after the last term: G staged as [LINES][P] reals, then its x spectra [Z][KH1][WS]
@@ -56,6 +78,7 @@ struct Cfg {
   static constexpr size_t lds_bytes = (w_bytes > gst_bytes + spec_bytes) ? w_bytes : gst_bytes + spec_bytes;
   static_assert(P % S == 0, "slab count must divide P");
   static_assert(P % 2 == 0, "half lines need an even P");
+  static_assert(NCH * Z <= NRL, "layout rows too few for this schedule");
   static_assert(lds_bytes <= 160 * 1024, "slab stage buffer exceeds LDS");
   static_assert(NT <= 1024, "too many threads per slab");
 };
@@ -112,12 +135,12 @@ __device__ __forceinline__ void pair_kxy(int p, int& kx, int& ky) {
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_forward_f(const T* __restrict__ f, cpx<T>* __restrict__ fhat,
                                                    cpx<T>* __restrict__ scratch) {
-  using C = Cfg<T, N>;
+  using C = Grid<T, N>;
   constexpr int K = C::K, Kh = C::Kh, NPAIR = C::NPAIR;
   const int cell = blockIdx.x;
   const T* fc = f + size_t(cell) * N * N * N;
   cpx<T>* sc = scratch + size_t(cell) * N * N * N;
-  cpx<T>* fh = fhat + size_t(cell) * C::NR * NPAIR;
+  cpx<T>* fh = fhat + size_t(cell) * C::NRL * NPAIR;
   // z pass: [x][y][z] real -> sc[x][y][kz]
   for (int it = threadIdx.x; it < N * N; it += blockDim.x) {
     cpx<T> a[N];
@@ -157,16 +180,16 @@ __global__ __launch_bounds__(256) void k_forward_f(const T* __restrict__ f, cpx<
   }
   // zero rows: the Nyquist mode k_z = -N/2 and the chunk padding
   for (int i = threadIdx.x; i < NPAIR; i += blockDim.x) fh[i] = cpx<T>{T(0), T(0)};
-  for (int i = threadIdx.x; i < (C::NR - N) * NPAIR; i += blockDim.x) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
+  for (int i = threadIdx.x; i < (C::NRL - N) * NPAIR; i += blockDim.x) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
 }
 
 // ------------------------------------------------------------------------------------
 // kernel 2: one slab of one cell, all separable terms
-template <typename T, int N, int RID>
+template <typename T, int N, int S, int RID>
 __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T* __restrict__ tab,
                                           int n_terms, T* __restrict__ Gw, cpx<T>* __restrict__ D,
                                           cpx<T>* W) {
-  using C = Cfg<T, N>;
+  using C = Cfg<T, N, S>;
   constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
   constexpr int NT = C::NT;
   const int tid = threadIdx.x;
@@ -182,10 +205,10 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   }
 
   constexpr uint32_t row_bytes = uint32_t(NPAIR) * sizeof(cpx<T>);  // one k_z row, fhat and tables
-  const __amdgpu_buffer_rsrc_t rf = make_rsrc(fh, uint32_t(C::NR) * row_bytes);
-  const __amdgpu_buffer_rsrc_t rt = make_rsrc(tab, uint32_t(n_terms) * C::NR * row_bytes);
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(fh, uint32_t(C::NRL) * row_bytes);
+  const __amdgpu_buffer_rsrc_t rt = make_rsrc(tab, uint32_t(n_terms) * C::NRL * row_bytes);
   for (int t = 0; t < n_terms; ++t) {
-    const uint32_t tterm = uint32_t(t) * C::NR * row_bytes;
+    const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
     // Every stage takes an opaque copy of the thread index (opaque_tid): its index
     // arithmetic is redone where it is used instead of being hoisted out of the term
     // loop or shared between stages and kept live next to the accumulator (LDS plane
@@ -372,12 +395,12 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__((Cfg<T, N>::NT)) void k_slab(const cpx<T>* __restrict__ fhat,
-                                                        const T* __restrict__ tab, int n_terms,
-                                                        T* __restrict__ G, cpx<T>* __restrict__ D,
-                                                        int xcd_map) {
-  using C = Cfg<T, N>;
+template <typename T, int N, int S>
+__global__ __launch_bounds__((Cfg<T, N, S>::NT)) void k_slab(const cpx<T>* __restrict__ fhat,
+                                                           const T* __restrict__ tab, int n_terms,
+                                                           T* __restrict__ G, cpx<T>* __restrict__ D,
+                                                           int xcd_map) {
+  using C = Cfg<T, N, S>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cpx<T>* W = reinterpret_cast<cpx<T>*>(lds_raw);
   // Workgroups are dealt round-robin to the 8 XCDs; with xcd_map the S slabs of one cell
@@ -392,11 +415,11 @@ __global__ __launch_bounds__((Cfg<T, N>::NT)) void k_slab(const cpx<T>* __restri
     cell = b / C::S;
     r = b % C::S;
   }
-  const cpx<T>* fh = fhat + size_t(cell) * C::NR * C::NPAIR;
+  const cpx<T>* fh = fhat + size_t(cell) * C::NRL * C::NPAIR;
   T* Gs = C::GREG ? nullptr : G + (size_t(cell) * C::S + r) * (size_t(C::Z) * C::P * C::P);
   cpx<T>* Ds = D + (size_t(cell) * C::S + r) * (size_t(C::KH1) * C::K * C::Z);
   static_for<0, C::S>([&](auto rid) {
-    if (r == decltype(rid)::value) slab_body<T, N, decltype(rid)::value>(fh, tab, n_terms, Gs, Ds, W);
+    if (r == decltype(rid)::value) slab_body<T, N, S, decltype(rid)::value>(fh, tab, n_terms, Gs, Ds, W);
   });
 }
 
@@ -419,11 +442,11 @@ __device__ __forceinline__ void block_reduce5(double (&v)[5], double* red) {
   __syncthreads();
 }
 
-template <typename T, int N>
+template <typename T, int N, int S_>
 __global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cpx<T>* __restrict__ scratch,
                                                 const T* f_in, T* q, T* f_out, double dt,
                                                 double* __restrict__ moments, EpiParams ep) {
-  using C = Cfg<T, N>;
+  using C = Cfg<T, N, S_>;
   constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, Z = C::Z, S = C::S;
   constexpr size_t N3 = size_t(N) * N * N;
   __shared__ double red[5 * 16];
@@ -581,9 +604,9 @@ hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, v
 
 // ------------------------------------------------------------------------------------
 // host launchers
-template <typename T, int N>
-static hipError_t launch_collide_impl(const CollideArgs& a) {
-  using C = Cfg<T, N>;
+template <typename T, int N, int S>
+static hipError_t launch_collide_sched(const CollideArgs& a) {
+  using C = Cfg<T, N, S>;
   const T* f = static_cast<const T*>(a.f);
   cpx<T>* fhat = static_cast<cpx<T>*>(a.ws_fhat);
   cpx<T>* scr = static_cast<cpx<T>*>(a.ws_scratch);
@@ -593,7 +616,7 @@ static hipError_t launch_collide_impl(const CollideArgs& a) {
   const int cells = int(a.n_cells);
   static bool lds_attr_set = false;  // dynamic LDS above 64 KB must be opted into per kernel
   if (!lds_attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_slab<T, N>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_slab<T, N, S>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(C::lds_bytes));
     if (e != hipSuccess) return e;
     lds_attr_set = true;
@@ -602,14 +625,35 @@ static hipError_t launch_collide_impl(const CollideArgs& a) {
   hipLaunchKernelGGL((k_forward_f<T, N>), dim3(cells), dim3(256), 0, st, f, fhat, scr);
   prof_mark(kProfForward, false, st);
   prof_mark(kProfSlab, true, st);
-  hipLaunchKernelGGL((k_slab<T, N>), dim3(cells * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
-                     static_cast<const T*>(a.tables), a.n_terms, G, D, (cells % 8 == 0) ? 1 : 0);
+  const int xcd = (a.xcd_map && cells % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_slab<T, N, S>), dim3(cells * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
+                     static_cast<const T*>(a.tables), a.n_terms, G, D, xcd);
   prof_mark(kProfSlab, false, st);
   prof_mark(kProfFinish, true, st);
-  hipLaunchKernelGGL((k_finish<T, N>), dim3(cells), dim3(256), 0, st, D, scr,
+  hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, scr,
                      static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
                      a.moments, a.ep);
   prof_mark(kProfFinish, false, st);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t launch_collide_impl(const CollideArgs& a) {
+  using V = Variants<T, N>;
+  if (a.variant == 0) return launch_collide_sched<T, N, V::s[0]>(a);
+  if constexpr (V::count > 1) {
+    if (a.variant == 1) return launch_collide_sched<T, N, V::s[1]>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N>
+static hipError_t launch_forward_impl(const void* f, void* fhat, void* scratch, int64_t cells, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  prof_mark(kProfForward, true, st);
+  hipLaunchKernelGGL((k_forward_f<T, N>), dim3(unsigned(cells)), dim3(256), 0, st, static_cast<const T*>(f),
+                     static_cast<cpx<T>*>(fhat), static_cast<cpx<T>*>(scratch));
+  prof_mark(kProfForward, false, st);
   return hipGetLastError();
 }
 
@@ -625,16 +669,17 @@ static hipError_t launch_moments_impl(const void* f, int64_t cells, double* u, d
 
 template <typename T, int N>
 static void sizes_impl(SlabGeometry* g) {
-  using C = Cfg<T, N>;
-  g->P = C::P;
-  g->S = C::S;
-  g->Z = C::Z;
-  g->fhat_elems = size_t(C::NR) * C::NPAIR;
-  g->table_rows = C::NR;
+  using Gd = Grid<T, N>;
+  using V = Variants<T, N>;
+  g->P = Gd::P;
+  g->n_variants = V::count;
+  for (int i = 0; i < 2; ++i) g->variant_slabs[i] = i < V::count ? V::s[i] : 0;
+  g->fhat_elems = size_t(Gd::NRL) * Gd::NPAIR;
+  g->table_rows = Gd::NRL;
   g->scratch_elems = size_t(N) * N * N;
-  g->g_elems = C::GREG ? 1 : size_t(C::S) * C::Z * C::P * C::P;
-  g->npair = C::NPAIR;
-  g->d_elems = size_t(C::S) * C::KH1 * C::K * C::Z;
+  g->g_elems = sizeof(T) == 4 ? 1 : size_t(Gd::P) * Gd::P * Gd::P;  // S*Z*P*P = P^3 for any S
+  g->npair = Gd::NPAIR;
+  g->d_elems = size_t(Gd::KH1) * Gd::K * Gd::P;  // S*KH1*K*Z = KH1*K*P for any S
 }
 
 #define FKS_DISPATCH_N(T, n, CALL) \
@@ -657,6 +702,18 @@ hipError_t launch_collide(int dtype_is_f32, int n, const CollideArgs& a) {
     FKS_DISPATCH_N(double, n, CALL_C)
   }
 #undef CALL_C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_forward(int dtype_is_f32, int n, const void* f, void* fhat, void* scratch, int64_t cells,
+                          void* stream) {
+#define CALL_F(T, nn) launch_forward_impl<T, nn>(f, fhat, scratch, cells, stream)
+  if (dtype_is_f32) {
+    FKS_DISPATCH_N(float, n, CALL_F)
+  } else {
+    FKS_DISPATCH_N(double, n, CALL_F)
+  }
+#undef CALL_F
   return hipErrorInvalidValue;
 }
 

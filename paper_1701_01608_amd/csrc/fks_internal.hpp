@@ -33,10 +33,14 @@ struct CollideArgs {
   double* moments;   // [cells][5] or null
   EpiParams ep;
   void* stream;
+  int variant;  // slab schedule index (SlabGeometry::variant_slabs)
+  int xcd_map;  // 1: keep the S slabs of a cell on one XCD
 };
 
 struct SlabGeometry {
-  int P, S, Z;
+  int P;
+  int n_variants;        // compiled slab schedules for this (dtype, n)
+  int variant_slabs[2];  // slab count S of each schedule
   size_t fhat_elems;     // complex elements per cell
   size_t scratch_elems;  // complex elements per cell
   size_t g_elems;        // real elements per cell
@@ -54,6 +58,28 @@ void slab_geometry(int dtype_is_f32, int n, SlabGeometry* g);
 hipError_t launch_collide(int dtype_is_f32, int n, const CollideArgs& a);
 hipError_t launch_moments(int dtype_is_f32, int n, const void* f, int64_t cells, double* u, double L,
                           double dv, void* stream);
+
+// forward transform of f only (fhat into the workspace layout)
+hipError_t launch_forward(int dtype_is_f32, int n, const void* f, void* fhat, void* scratch, int64_t cells,
+                          void* stream);
+
+// surrogate kernels
+enum { kEpiF32_ = 0, kEpiBiasSilu_ = 1, kEpiDSilu_ = 2, kEpiBiasBf16_ = 3 };
+hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B, int M, int N, int K, int lda,
+                       int ldb, const float* bias, float* Cf, void* Ch, const float* Zin, int ldc, void* stream);
+hipError_t launch_mse(const float* Y, const float* T, void* dY, int64_t n, double* partial, int blocks, void* stream);
+hipError_t launch_sum_partials(const double* partial, int n, double* out, void* stream);
+hipError_t launch_colsum(const void* X, int rows, int cols, float* out, void* stream);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, void* stream);
+hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int half, int npair, int K, int Kh, int mh,
+                           double box3, void* X, int ldx, float* rho, int64_t cells, void* stream);
+hipError_t launch_sur_output(const float* Y, int ldy, const float* rho, float scale, int n, double L, float* q, double* r,
+                             int64_t cells, void* stream);
+hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, float* t, int n3, int64_t cells, void* stream);
+hipError_t launch_compact(const double* r, int cells, double thr, int* list, int* count, void* stream);
+hipError_t launch_gather_cells(int scatter, const float* src, float* dst, const int* list, int count, int n3,
+                               void* stream);
 
 // f = (f + g) / 2 elementwise over n values
 hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, void* stream);

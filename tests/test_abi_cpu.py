@@ -101,3 +101,25 @@ def test_transport_create_validation(lib):
     assert L.fks_xport_sizes(h, ctypes.byref(sb)) == 0 and sb.value >= 16 ** 3 * 48
     assert L.fks_transport(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1, 0.1, None) == -5
     L.fks_xport_destroy(h)
+
+
+def test_surrogate_create_validation(lib):
+    L = lib.lib()
+    h = ctypes.c_void_p()
+    # modes odd / too large, width not a multiple of 128, batch not a multiple of 128, bad scale
+    assert L.fks_sur_create(32, 7, 1024, 1024, 1.0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 32, 1024, 1024, 1.0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1000, 1024, 1.0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1024, 1000, 1.0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1024, 1024, 0.0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(12, 4, 128, 128, 1.0, ctypes.byref(h)) == -2   # 12^3 not a multiple of 128
+    assert L.fks_sur_create(32, 8, 1024, 1024, 1.0, ctypes.byref(h)) == 0
+    pb, wb, npar = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
+    assert L.fks_sur_sizes(h, ctypes.byref(pb), ctypes.byref(wb), ctypes.byref(npar)) == 0
+    n_in, w, n_out = 1024, 1024, 32 ** 3
+    assert npar.value == n_in * w + w + w * w + w + n_out * w + n_out
+    assert pb.value >= npar.value * (4 * 4 + 2)      # master, m, v, grad (FP32) + BF16 copy
+    assert wb.value >= 1024 * n_out * 4              # FP32 outputs of one batch
+    # calls before bind
+    assert L.fks_sur_forward(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 128, None) == -5
+    L.fks_sur_destroy(h)

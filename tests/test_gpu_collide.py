@@ -180,3 +180,69 @@ def test_full_batch_4096_sampled():
     mass = np.abs(qn.sum(axis=(1, 2, 3))) / np.abs(qn).sum(axis=(1, 2, 3))
     print(f"mass/sum|Q|: median {np.median(mass):.2e} max {mass.max():.2e}", flush=True)
     assert np.median(mass) <= 1e-6 and mass.max() <= 1e-4
+
+
+@pytest.mark.parametrize("n", [16, 24, 32])
+def test_every_schedule_matches_oracle(n):
+    plan = gpu_plan(n, "f32", max_cells=8)
+    f = fks_inputs.maxwellian_mixture(n, 8.0, 8, seed=300 + n)
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ref, _ = oracle_q(ft.double().cpu().numpy(), n)
+    from paper_1701_01608_amd import _lib
+    import ctypes
+    seen = 0
+    for slabs in (1, 2, 3, 4, 6, 8, 9, 12):
+        for xcd in (0, 1):
+            st = _lib.lib().fks_plan_set_schedule(plan.handle, slabs, xcd)
+            if st != 0:
+                continue
+            seen += 1
+            q = plan.collide(ft)
+            torch.cuda.synchronize()
+            err = rel(q.double().cpu().numpy(), ref)
+            print(f"n={n} slabs={slabs} xcd={xcd} rel-L2 {err:.2e}", flush=True)
+            assert err <= TOL["f32"]
+    assert seen >= 2
+
+
+def test_autotune_picks_a_schedule_and_caches(tmp_path):
+    n = 32
+    plan = gpu_plan(n, "f32", max_cells=64)
+    f = fks_inputs.maxwellian_mixture(n, 8.0, 64, seed=77)
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    cache = str(tmp_path / "fks_schedules.jsonl")
+    sched = plan.autotune(ft, cache_path=cache)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"slabs":%d' % sched[0] in lines[0]
+    plan2 = gpu_plan(n, "f32", max_cells=64)
+    assert plan2.autotune(ft, cache_path=cache) == sched     # served from the cache
+    assert len(open(cache).read().strip().splitlines()) == 1
+    q = plan2.collide(ft[:4].contiguous())
+    torch.cuda.synchronize()
+    ref, _ = oracle_q(ft[:4].double().cpu().numpy(), n)
+    assert rel(q.double().cpu().numpy(), ref) <= TOL["f32"]
+
+
+def test_uneven_batch_as_one_graph():
+    from paper_1701_01608_amd import Graph, collide_grouped
+    fs, plans, qs = [], [], []
+    for n, seed in ((16, 11), (24, 12), (32, 13)):
+        plans.append(gpu_plan(n, "f32", a1=3, a2=4, max_cells=16))
+        fs.append(torch.tensor(fks_inputs.maxwellian_mixture(n, 8.0, 16, seed=seed), dtype=torch.float32,
+                               device="cuda"))
+        qs.append(torch.zeros_like(fs[-1]))
+    eager = collide_grouped(plans, fs)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with Graph(s) as g:
+            collide_grouped(plans, fs, qs, stream=s)
+    for rep in range(3):
+        for q in qs:
+            q.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.launch()
+        s.synchronize()
+        for q, e in zip(qs, eager):
+            assert torch.equal(q, e), f"replay {rep}"

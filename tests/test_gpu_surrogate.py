@@ -1,0 +1,210 @@
+"""GPU tests of the Fourier-mode MLP surrogate (BF16 MFMA training and inference) against
+the FP64 oracle of oracle/mlp.py, called through the C ABI.
+
+Tolerances: the GEMM operands are BF16 (unit roundoff 2^-9 with round to nearest), the
+products accumulate in FP32.  Per layer the inputs and weights are rounded once each and
+the activations once more, so a layer's output carries ~3 * 2^-9 ~ 6e-3 relative error
+per element, averaged down over the dot products; the checks use 1e-2 (forward) and
+3e-2 (gradients, one more rounding of dY and dZ) in relative L2 norm.  The oracle is run
+on the BF16-rounded weights and inputs, so only the internal roundings remain.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_round(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _tiny(seed=5, width=128):
+    import paper_1701_01608_amd as fks
+    from oracle import mlp
+    sur = fks.Surrogate(n=8, modes=4, width=width, max_batch=256)
+    params = mlp.init_params([sur.n_in, width, width, sur.n_out], seed)
+    rng = np.random.default_rng(seed + 100)
+    params[1] = rng.normal(0, 0.1, params[1].shape)
+    params[3] = rng.normal(0, 0.1, params[3].shape)
+    params[5] = rng.normal(0, 0.1, params[5].shape)
+    sur.set_params(params)
+    return sur, params
+
+
+def test_forward_matches_oracle():
+    from oracle import mlp
+    sur, params = _tiny()
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((256, sur.n_in))
+    xd = torch.as_tensor(x, dtype=torch.float32).to(torch.bfloat16).cuda()
+    y = sur.forward(xd).cpu().numpy()
+    pr = [_bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
+    y_ref, _ = mlp.forward(pr, _bf16_round(x))
+    err = _rel(y, y_ref)
+    print(f"forward rel-L2 {err:.3e}")
+    assert err <= 1e-2
+
+
+def test_gradients_match_oracle():
+    from oracle import mlp
+    sur, params = _tiny(seed=6)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((128, sur.n_in))
+    t = rng.standard_normal((128, sur.n_out)) * 0.5
+    xd = torch.as_tensor(x, dtype=torch.float32).to(torch.bfloat16).cuda()
+    td = torch.as_tensor(t, dtype=torch.float32).cuda()
+    loss = sur.train_step(xd, td, lr=0.0, update=False)
+    torch.cuda.synchronize()
+    g = sur.get_grads()
+    pr = [_bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
+    loss_ref, g_ref = mlp.loss_and_grads(pr, _bf16_round(x), t)
+    assert abs(loss.item() - loss_ref) <= 1e-2 * loss_ref
+    names = ["W1", "b1", "W2", "b2", "W3", "b3"]
+    for name, a, b in zip(names, g, g_ref):
+        err = _rel(a, b)
+        print(f"grad {name} rel-L2 {err:.3e}")
+        assert err <= 3e-2, name
+    # parameters untouched without update
+    p_after = sur.get_params()
+    for a, b in zip(p_after, params):
+        assert np.array_equal(a, np.asarray(b, dtype=np.float32))
+
+
+def test_adam_step_matches_oracle():
+    from oracle import mlp
+    sur, params = _tiny(seed=7)
+    rng = np.random.default_rng(13)
+    x = torch.as_tensor(rng.standard_normal((128, sur.n_in)), dtype=torch.float32).to(torch.bfloat16).cuda()
+    t = torch.as_tensor(rng.standard_normal((128, sur.n_out)), dtype=torch.float32).cuda()
+    p32 = [np.asarray(p, dtype=np.float32).astype(np.float64) for p in params]
+    opt = mlp.Adam(p32, lr=1e-3)
+    for _ in range(3):
+        sur.train_step(x, t, lr=1e-3, update=True)
+        torch.cuda.synchronize()
+        g = [a.astype(np.float64) for a in sur.get_grads()]
+        p32 = opt.step(p32, g)
+        got = sur.get_params()
+        for a, b in zip(got, p32):
+            # FP32 update arithmetic against FP64: a few ulps of the parameter
+            assert np.max(np.abs(a - b)) <= 1e-6 * max(1.0, np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("n,modes,dtype", [(8, 4, "f32"), (16, 8, "f64"), (32, 8, "f32")])
+def test_features_match_oracle(n, modes, dtype):
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians
+    from oracle import mlp
+    L = 8.0 if n >= 16 else 4.0
+    f = perturbed_maxwellians(n, L, 5, seed=21)
+    plan = fks.Plan(n=n, L=L, R=L * 4 / (3 + 2 ** 0.5), a1=2, a2=2, dtype=dtype, max_cells=4)
+    sur = fks.Surrogate(n=n, modes=modes, width=128, max_batch=128)
+    fd = torch.as_tensor(f, dtype=plan.torch_dtype).cuda().contiguous()
+    x, rho = sur.features(plan, fd)
+    x = x.float().cpu().numpy()
+    rho = rho.cpu().numpy()
+    for c in range(5):
+        xr, rr = mlp.features(f[c], L, modes)
+        # BF16 storage: 2^-8 relative to the magnitude (|x| <= 1), plus FP32 transform error
+        assert np.max(np.abs(x[c] - xr)) <= 2.0 ** -8 * np.max(np.abs(xr)) + 1e-6
+        assert abs(rho[c] - rr) <= 1e-6 * rr
+
+
+def test_infer_indicator_and_fallback():
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians
+    from oracle import mlp
+    n, L, cells = 16, 8.0, 200
+    f = perturbed_maxwellians(n, L, cells, seed=3)
+    plan = fks.Plan(n=n, L=L, R=6.0, a1=4, a2=4, dtype="f32", max_cells=64)
+    sur = fks.Surrogate(n=n, modes=8, width=128, max_batch=128)
+    sur.set_params(mlp.init_params([sur.n_in, 128, 128, sur.n_out], 9))
+    fd = torch.as_tensor(f, dtype=torch.float32).cuda().contiguous()
+    q_spec = plan.collide(fd)
+    r = torch.empty(cells, dtype=torch.float64, device="cuda")
+    # no fallback: q = rho^2 y, indicator from the FP64 moments of q
+    q_sur, nf = sur.infer(plan, fd, threshold=-1.0, indicator=r)
+    assert nf == 0
+    x, rho = sur.features(plan, fd)
+    xp = torch.zeros((256, sur.n_in), dtype=torch.bfloat16, device="cuda")
+    xp[:cells] = x
+    y = sur.forward(xp)[:cells]
+    expect = (y * (rho * rho)[:, None]).reshape(cells, n, n, n)
+    assert torch.allclose(q_sur, expect, rtol=1e-6, atol=0.0)
+    qs = q_sur.double().cpu().numpy()
+    rr = r.cpu().numpy()
+    for c in range(0, cells, 37):
+        assert abs(rr[c] - mlp.moment_indicator(qs[c], L)) <= 1e-9 + 1e-6 * rr[c]
+    # threshold at the median: exactly the cells above it take the spectral Q
+    thr = float(np.median(rr))
+    q_h, nf = sur.infer(plan, fd, threshold=thr)
+    above = rr > thr
+    assert nf == int(above.sum())
+    torch.cuda.synchronize()
+    a = torch.as_tensor(above, device="cuda")
+    assert torch.equal(q_h[a], q_spec[a])
+    assert torch.equal(q_h[~a], q_sur[~a])
+    # threshold 0 on an untrained net: every cell falls back, result = spectral Q
+    q_all, nf = sur.infer(plan, fd, threshold=0.0)
+    assert nf == cells
+    assert torch.equal(q_all, q_spec)
+
+
+def test_training_learns_operator():
+    """Train on perturbed Maxwellians labelled by the FP32 spectral path (n = 16), then
+    check the held-out error against the oracle's Q on sampled cells, and that the
+    indicator ranks cells by their true error."""
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians
+    from oracle import mlp
+    from oracle.collide import collide_fast
+    from oracle.tables import make_plan
+    n, L, R = 16, 8.0, 6.0
+    plan = fks.Plan(n=n, L=L, R=R, a1=4, a2=4, dtype="f32", max_cells=1024)
+    width = 512
+    sur = fks.Surrogate(n=n, modes=8, width=width, max_batch=1024, out_scale=3e-3)
+    sur.set_params(mlp.init_params([sur.n_in, width, width, sur.n_out], 1))
+    n_train = 8192
+    f_tr = torch.as_tensor(perturbed_maxwellians(n, L, n_train, seed=1), dtype=torch.float32).cuda()
+    x_tr, rho_tr = sur.features(plan, f_tr)
+    t_tr = sur.targets(plan.collide(f_tr).reshape(n_train, -1), rho_tr)
+    del f_tr
+    batch, steps = 256, 1500
+    losses = []
+    for s in range(steps):
+        j = (s * batch) % n_train
+        lr = 1e-3 if s < 1000 else 3e-4
+        loss = sur.train_step(x_tr[j:j + batch], t_tr[j:j + batch], lr=lr)
+        if s % 100 == 0 or s == steps - 1:
+            losses.append(loss.item())
+    print("losses", ["%.3e" % v for v in losses])
+    assert losses[-1] < 0.05 * losses[0]
+    # held-out cells (seed 2): surrogate vs oracle Q on a sample
+    n_val = 256
+    f_val_np = perturbed_maxwellians(n, L, n_val, seed=2)
+    f_val = torch.as_tensor(f_val_np, dtype=torch.float32).cuda()
+    r = torch.empty(n_val, dtype=torch.float64, device="cuda")
+    q_sur, _ = sur.infer(plan, f_val, threshold=-1.0, indicator=r)
+    q_spec = plan.collide(f_val)
+    err = ((q_sur - q_spec).double().flatten(1).norm(dim=1) / q_spec.double().flatten(1).norm(dim=1)).cpu().numpy()
+    print("surrogate per-cell rel-L2: median %.3e max %.3e" % (np.median(err), err.max()))
+    oplan = make_plan(n, L, R, a1=4, a2=4)
+    for c in range(0, n_val, 85):
+        q_ref = collide_fast(f_val_np[c], oplan)
+        e_ref = np.linalg.norm(q_sur[c].double().cpu().numpy() - q_ref) / np.linalg.norm(q_ref)
+        assert abs(e_ref - err[c]) <= 1e-4 + 1e-3 * err[c]  # spectral FP32 Q is within 1e-5 of the oracle
+    assert np.median(err) < 0.2
+    # the indicator ranks cells by true error (Spearman rank correlation)
+    rr = r.cpu().numpy()
+    ra = np.argsort(np.argsort(rr))
+    ea = np.argsort(np.argsort(err))
+    rho_s = np.corrcoef(ra, ea)[0, 1]
+    print("indicator/error rank correlation %.3f" % rho_s)
+    assert rho_s > 0.3
