@@ -123,6 +123,42 @@ def bench_uneven(fks, torch, dev, reps=10):
             "schedules": [p.schedule() for p in plans]}
 
 
+def bench_bkw(fks, torch, dev, steps=100, dt=0.01):
+    """Space-homogeneous BKW run: Maxwell molecules (B = 1/(4 pi)), n = 16, L = 8, R = 6,
+    6 directions (2 x 3) x 8 radial Gauss-Legendre nodes, FP64, Heun steps from
+    f_BKW(t0 = 5.5); the 100 steps are recorded once as a hipGraph and launched."""
+    import fks_inputs
+    from oracle import bkw
+    n, t0 = 16, 5.5
+    plan = fks.Plan(n, L, R, kernel="vhs", alpha=0.0, C=1.0 / (4.0 * np.pi), a1=2, a2=3, n_radial=8,
+                    dtype="f64", max_cells=1)
+    f0 = torch.tensor(fks_inputs.bkw_initial(n, L, t0)[None], device=dev)
+    f = f0.clone()
+    tmp = (torch.empty_like(f), torch.empty_like(f))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with fks.Graph(s) as g:
+            plan.heun(f, dt, n_steps=steps, tmp=tmp, stream=s)
+        f.copy_(f0)
+        g.launch()                                   # warm-up replay
+        f.copy_(f0)
+    s.synchronize()
+    t1 = time.perf_counter()
+    with torch.cuda.stream(s):
+        g.launch()
+    s.synchronize()
+    wall = time.perf_counter() - t1
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    exact = bkw.f_bkw(t0 + steps * dt, V)
+    got = f[0].cpu().numpy()
+    return {"workload": "BKW, Maxwell molecules, n=16, 6 directions x 8 radial nodes (48 terms), FP64, "
+                        "100 Heun steps (200 Q evaluations) in one hipGraph",
+            "ms_total": round(wall * 1e3, 3), "us_per_q": round(wall * 1e6 / (2 * steps), 2),
+            "rel_l2_vs_closed_form": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+
+
 def bench_fks_step(fks, torch, dev, steps=20):
     """One GPU's share of the 3D/3D FKS run: 32^3 cells x 32^3 velocities, FP32, periodic box
     [0,2)^3, f = (1 + 0.1 sin(pi x1)) M_{1,0,1}(v), hard spheres M = 16, dt = 0.004375;
@@ -161,7 +197,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the 32^3-cell FKS step workload")
+    ap.add_argument("--no-extras", action="store_true", help="skip the uneven-batch, box-step and surrogate workloads")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default slab schedule (profiling runs: no extra dispatches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -193,7 +231,8 @@ def main():
     f = torch.tensor(f64, dtype=torch.float32, device=dev)
     plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=CELLS)
     q = torch.empty_like(f)
-    schedule = plan.autotune(f, q)      # slab count x XCD mapping, timed on this batch
+    # slab count x XCD mapping, timed on this batch
+    schedule = plan.schedule() if args.no_autotune else plan.autotune(f, q)
     for _ in range(args.warmup):
         plan.collide(f, q)
     torch.cuda.synchronize()
@@ -257,6 +296,7 @@ def main():
         del plan64, fd, qd
 
     if not args.no_extras:
+        out["bkw_maxwell"] = bench_bkw(fks, torch, dev)
         out["uneven_batch"] = bench_uneven(fks, torch, dev)
         out["fks_step_box"] = bench_fks_step(fks, torch, dev)
     if cpu is not None:

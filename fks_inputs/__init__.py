@@ -66,6 +66,28 @@ def perturbed_maxwellians(n, L, n_cells, seed=1, amp=0.3):
     return (1.0 - a)[:, None, None, None] * m1 + a[:, None, None, None] * m2
 
 
+def perturbed_maxwellians_device(n, L, n_cells, seed=1, amp=0.3, device="cuda", dtype=None):
+    """perturbed_maxwellians with the same seeded parameters, evaluated on a torch device
+    (large training sets without the host round trip).  Returns (n_cells, n, n, n)."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 1.5, (n_cells, 2))
+    u = rng.standard_normal((n_cells, 2, 3))
+    T = rng.uniform(0.5, 2.0, (n_cells, 2))
+    a = rng.uniform(0.0, amp, n_cells)
+    v = torch.as_tensor(velocity_axis(n, L), dtype=torch.float64, device=device)
+    out = torch.zeros((n_cells, n, n, n), dtype=torch.float64, device=device)
+    w = np.stack([1.0 - a, a], axis=1)
+    for m in range(2):
+        uu = torch.as_tensor(u[:, m], device=device)
+        TT = torch.as_tensor(T[:, m], device=device)[:, None]
+        g = [torch.exp(-(v[None, :] - uu[:, d:d + 1]) ** 2 / (2.0 * TT)) for d in range(3)]
+        norm = torch.as_tensor(w[:, m] * rho[:, m] * (2.0 * np.pi * T[:, m]) ** -1.5, device=device)
+        out += norm[:, None, None, None] * g[0][:, :, None, None] * g[1][:, None, :, None] * g[2][:, None, None, :]
+    return out.to(dtype)
+
+
 def wave_box(n, L, shape, amp=0.1, rho0=1.0, T0=1.0):
     """Cells of a periodic box [0,2)^3 (dx = 2/nx): f = (1 + amp sin(pi x1)) M_{1,0,1}(v).
 

@@ -1032,6 +1032,7 @@ fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t
   if (st != FKS_OK) return st;
   if (p->n != s->n || p->d.dtype != FKS_F32) return fail(FKS_E_ARG, "fallback plan must be FP32 on the same grid");
   if (n_cells < 0 || (n_cells > 0 && (!f || !q))) return fail(FKS_E_ARG, "bad buffers");
+  if (n_cells > 0 && ranges_overlap(f, q, size_t(n_cells) * s->fout * 4)) return fail(FKS_E_ARG, "q must not overlap f");
   if (n_fallback) *n_fallback = 0;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const int n3 = s->fout;

@@ -183,6 +183,79 @@ __global__ __launch_bounds__(256) void k_forward_f(const T* __restrict__ f, cpx<
   for (int i = threadIdx.x; i < (C::NRL - N) * NPAIR; i += blockDim.x) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
 }
 
+// LDS-resident forward transform: the real z rows are reduced to k_z = 0..N/2-1 (the
+// negative k_z follow by Hermitian symmetry), so one cell's partial spectra
+// [x][y][k_z] (row stride padded by one) fit in LDS and f is read once, fhat written once.
+template <typename T, int N>
+struct FwdLds {
+  static constexpr int KH1 = N / 2;
+  static constexpr int RS = KH1 + 1;
+  static constexpr size_t bytes = size_t(N) * N * RS * sizeof(cpx<T>);
+  static constexpr bool fits = bytes <= 156 * 1024;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_forward_lds(const T* __restrict__ f, cpx<T>* __restrict__ fhat) {
+  using C = Grid<T, N>;
+  using F = FwdLds<T, N>;
+  constexpr int K = C::K, Kh = C::Kh, KH1 = F::KH1, RS = F::RS, NPAIR = C::NPAIR, H = N / 2;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cpx<T>* sm = reinterpret_cast<cpx<T>*>(lds_raw);
+  const int cell = blockIdx.x;
+  const T* fc = f + size_t(cell) * N * N * N;
+  cpx<T>* fh = fhat + size_t(cell) * C::NRL * NPAIR;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // z pass: real rows (x, y) -> k_z = 0..N/2-1
+  for (int it = tid; it < N * N; it += nt) {
+    T r[N];
+    const T* row = fc + size_t(it) * N;
+    static_for<0, N>([&](auto z) { r[z] = row[z]; });
+    cpx<T> o[KH1];
+    rdft_low<N, KH1>(r, o);
+    static_for<0, KH1>([&](auto kz) { sm[size_t(it) * RS + kz] = o[kz]; });
+  }
+  __syncthreads();
+  // y pass: columns (x, k_z), in place y -> k_y index k_y + Kh
+  for (int it = tid; it < N * KH1; it += nt) {
+    const int x = it / KH1, kz = it % KH1;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto y) { a[y] = sm[(size_t(x) * N + y) * RS + kz]; });
+    dft<N, -1>(a);
+    static_for<0, K>([&](auto kyi) {
+      sm[(size_t(x) * N + kyi) * RS + kz] = a[(decltype(kyi)::value - Kh + N) % N];
+    });
+  }
+  __syncthreads();
+  // x pass: lines (k_y, k_z >= 0); each value goes to its half-plane pencil, directly or
+  // (k_z > 0) as the conjugate of the mirrored mode (-k_x, -k_y, -k_z)
+  constexpr T scale = T(1.0 / (double(N) * N * N));
+  for (int it = tid; it < KH1 * K; it += nt) {
+    const int kz = it / K, kyi = it % K;
+    const int ky = kyi - Kh;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto x) { a[x] = sm[(size_t(x) * N + kyi) * RS + kz]; });
+    dft<N, -1>(a);
+    static_for<0, K>([&](auto kxi) {
+      constexpr int kx = decltype(kxi)::value - Kh;
+      const cpx<T> v = a[(kx + N) % N];
+      const cpx<T> sv = {v.re * scale, v.im * scale};
+      const bool direct = kx > 0 || (kx == 0 && ky >= 0);
+      if (direct) {
+        const int p = kx > 0 ? (kx - 1) * K + kyi : Kh * K + ky;
+        fh[size_t(kz + H) * NPAIR + p] = sv;
+        if (kx == 0 && ky == 0 && kz > 0) fh[size_t(H - kz) * NPAIR + p] = conj(sv);
+      } else if (kz > 0) {
+        const int mkx = -kx, mky = -ky;  // (mkx, mky) lies in the half plane
+        const int p = mkx > 0 ? (mkx - 1) * K + (mky + Kh) : Kh * K + mky;
+        fh[size_t(H - kz) * NPAIR + p] = conj(sv);
+      }
+    });
+  }
+  // zero rows: the Nyquist mode k_z = -N/2 and the chunk padding
+  for (int i = tid; i < NPAIR; i += nt) fh[i] = cpx<T>{T(0), T(0)};
+  for (int i = tid; i < (C::NRL - N) * NPAIR; i += nt) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
+}
+
 // ------------------------------------------------------------------------------------
 // kernel 2: one slab of one cell, all separable terms
 template <typename T, int N, int S, int RID>
@@ -555,6 +628,134 @@ __global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cp
   }
 }
 
+// LDS-resident finish: the kept spectrum (k_x >= 0) of one cell, [k_x][y][z] with the
+// z row padded by one, lives in LDS through the z, y and x syntheses; the x pass stores
+// its N real outputs in place of the N/2 complex inputs of its own line.
+template <typename T, int N>
+struct FinLds {
+  static constexpr int KH1 = N / 2;
+  static constexpr int RS = N + 1;
+  static constexpr size_t bytes = size_t(KH1) * N * RS * sizeof(cpx<T>);
+  static constexpr bool fits = bytes <= 156 * 1024;
+};
+
+template <typename T, int N, int S_>
+__global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D, const T* f_in, T* q, T* f_out,
+                                                    double dt, double* __restrict__ moments, EpiParams ep) {
+  using C = Cfg<T, N, S_>;
+  using F = FinLds<T, N>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, Z = C::Z, S = C::S, RS = F::RS;
+  static_assert(KH1 == F::KH1, "half spectrum size");
+  constexpr size_t N3 = size_t(N) * N * N;
+  __shared__ double red[5 * 16];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cpx<T>* sm = reinterpret_cast<cpx<T>*>(lds_raw);
+  const int cell = blockIdx.x;
+  const cpx<T>* Dc = D + size_t(cell) * S * (size_t(KH1) * K * Z);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr double inv_p3 = 1.0 / (double(P) * P * P);
+
+  // combine the S slab partials for every kept (kx >= 0, ky, kz), then z synthesis
+  for (int it = tid; it < KH1 * K; it += nt) {
+    const int kx = it / K, kyi = it % K;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto z) { a[z] = cpx<T>{T(0), T(0)}; });
+    static_for<0, K>([&](auto kzi) {
+      constexpr int kz = decltype(kzi)::value - Kh;
+      constexpr int b = ((kz % Z) + Z) % Z;
+      cpx<T> acc = {T(0), T(0)};
+      static_for<0, S>([&](auto r) {
+        const cpx<T> d = Dc[(size_t(decltype(r)::value) * KH1 * K + it) * Z + b];
+        acc = acc + twiddle<P, -1, long(kz) * decltype(r)::value>(d);
+      });
+      a[(kz + N) % N] = cpx<T>{T(acc.re * T(inv_p3)), T(acc.im * T(inv_p3))};
+    });
+    dft<N, +1>(a);
+    static_for<0, N>([&](auto z) { sm[(size_t(kx) * N + kyi) * RS + z] = a[z]; });
+  }
+  __syncthreads();
+  // y synthesis: columns (kx, z), in place ky -> y
+  for (int it = tid; it < KH1 * N; it += nt) {
+    const int kx = it / N, z = it % N;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
+    static_for<0, K>([&](auto kyi) {
+      a[(decltype(kyi)::value - Kh + N) % N] = sm[(size_t(kx) * N + kyi) * RS + z];
+    });
+    dft<N, +1>(a);
+    static_for<0, N>([&](auto y) { sm[(size_t(kx) * N + y) * RS + z] = a[y]; });
+  }
+  __syncthreads();
+  // x synthesis (Hermitian in kx) -> real Q, stored as pairs (Q[2j], Q[2j+1]) in slot
+  // (j, y, z); FP64 invariant moments of Q
+  double m[5] = {0, 0, 0, 0, 0};
+  for (int it = tid; it < N * N; it += nt) {
+    const int y = it / N, z = it % N;
+    cpx<T> a[N];
+    static_for<0, N>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
+    static_for<0, KH1>([&](auto kx) {
+      const cpx<T> v = sm[(size_t(decltype(kx)::value) * N + y) * RS + z];
+      a[kx] = v;
+      if constexpr (decltype(kx)::value > 0) a[N - decltype(kx)::value] = conj(v);
+    });
+    dft<N, +1>(a);
+    const double vy = -ep.L + y * ep.dv, vz = -ep.L + z * ep.dv;
+    static_for<0, N>([&](auto x) {
+      const double d = double(a[x].re);
+      const double vx = -ep.L + decltype(x)::value * ep.dv;
+      m[0] += d;
+      m[1] += vx * d;
+      m[2] += vy * d;
+      m[3] += vz * d;
+      m[4] += 0.5 * (vx * vx + vy * vy + vz * vz) * d;
+    });
+    static_for<0, KH1>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      sm[(size_t(jj) * N + y) * RS + z] = cpx<T>{a[2 * jj].re, a[2 * jj + 1].re};
+    });
+  }
+  __syncthreads();
+  double lam[5] = {0, 0, 0, 0, 0};
+  if (ep.conserve) {
+    block_reduce5(m, red);
+    for (int i = 0; i < 5; ++i) {
+      double sacc = 0.0;
+      for (int j = 0; j < 5; ++j) sacc += ep.minv[i * 5 + j] * m[j];
+      lam[i] = sacc;
+    }
+  }
+  const T* fi = f_in ? f_in + size_t(cell) * N3 : nullptr;
+  T* qo = q ? q + size_t(cell) * N3 : nullptr;
+  T* fo = f_out ? f_out + size_t(cell) * N3 : nullptr;
+  const T* smr = reinterpret_cast<const T*>(sm);
+  double u[5] = {0, 0, 0, 0, 0};
+  for (int i = tid; i < int(N3); i += nt) {
+    const int x = i / (N * N), y = (i / N) % N, z = i % N;
+    const double vx = -ep.L + x * ep.dv, vy = -ep.L + y * ep.dv, vz = -ep.L + z * ep.dv;
+    const double e = 0.5 * (vx * vx + vy * vy + vz * vz);
+    double qv = double(smr[(((size_t(x >> 1) * N + y) * RS + z) << 1) + (x & 1)]);
+    if (ep.conserve) qv -= lam[0] + lam[1] * vx + lam[2] * vy + lam[3] * vz + lam[4] * e;
+    if (qo) qo[i] = T(qv);
+    if (fo) {
+      const T nv = T(double(fi[i]) + dt * qv);
+      fo[i] = nv;
+      const double d = double(nv);
+      u[0] += d;
+      u[1] += vx * d;
+      u[2] += vy * d;
+      u[3] += vz * d;
+      u[4] += e * d;
+    }
+  }
+  if (moments && fo) {
+    block_reduce5(u, red);
+    if (tid == 0) {
+      const double w = ep.dv * ep.dv * ep.dv;
+      for (int i = 0; i < 5; ++i) moments[size_t(cell) * 5 + i] = u[i] * w;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // FP64 moments of f: dv^3 sum phi(v) f
 template <typename T, int N>
@@ -604,6 +805,29 @@ hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, v
 
 // ------------------------------------------------------------------------------------
 // host launchers
+
+// forward transform of a batch: the LDS-resident kernel where one cell's partial
+// spectra fit in LDS, else three passes through the per-cell global scratch
+template <typename T, int N>
+static hipError_t launch_forward_kernel(const T* f, cpx<T>* fhat, cpx<T>* scr, int cells, hipStream_t st) {
+  if constexpr (FwdLds<T, N>::fits) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_lds<T, N>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               int(FwdLds<T, N>::bytes));
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    (void)scr;
+    constexpr size_t lds = FwdLds<T, N>::bytes;
+    hipLaunchKernelGGL((k_forward_lds<T, N>), dim3(cells), dim3(512), lds, st, f, fhat);
+  } else {
+    hipLaunchKernelGGL((k_forward_f<T, N>), dim3(cells), dim3(256), 0, st, f, fhat, scr);
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int N, int S>
 static hipError_t launch_collide_sched(const CollideArgs& a) {
   using C = Cfg<T, N, S>;
@@ -622,17 +846,33 @@ static hipError_t launch_collide_sched(const CollideArgs& a) {
     lds_attr_set = true;
   }
   prof_mark(kProfForward, true, st);
-  hipLaunchKernelGGL((k_forward_f<T, N>), dim3(cells), dim3(256), 0, st, f, fhat, scr);
+  const hipError_t ef = launch_forward_kernel<T, N>(f, fhat, scr, cells, st);
   prof_mark(kProfForward, false, st);
+  if (ef != hipSuccess) return ef;
   prof_mark(kProfSlab, true, st);
   const int xcd = (a.xcd_map && cells % 8 == 0) ? 1 : 0;
   hipLaunchKernelGGL((k_slab<T, N, S>), dim3(cells * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
                      static_cast<const T*>(a.tables), a.n_terms, G, D, xcd);
   prof_mark(kProfSlab, false, st);
   prof_mark(kProfFinish, true, st);
-  hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, scr,
-                     static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
-                     a.moments, a.ep);
+  if constexpr (FinLds<T, N>::fits) {
+    static bool fin_attr_set = false;
+    if (!fin_attr_set) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_finish_lds<T, N, S>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               int(FinLds<T, N>::bytes));
+      if (e != hipSuccess) return e;
+      fin_attr_set = true;
+    }
+    constexpr size_t lds = FinLds<T, N>::bytes;
+    hipLaunchKernelGGL((k_finish_lds<T, N, S>), dim3(cells), dim3(512), lds, st, D,
+                       static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
+                       a.moments, a.ep);
+  } else {
+    hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, scr,
+                       static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
+                       a.moments, a.ep);
+  }
   prof_mark(kProfFinish, false, st);
   return hipGetLastError();
 }
@@ -651,10 +891,10 @@ template <typename T, int N>
 static hipError_t launch_forward_impl(const void* f, void* fhat, void* scratch, int64_t cells, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_mark(kProfForward, true, st);
-  hipLaunchKernelGGL((k_forward_f<T, N>), dim3(unsigned(cells)), dim3(256), 0, st, static_cast<const T*>(f),
-                     static_cast<cpx<T>*>(fhat), static_cast<cpx<T>*>(scratch));
+  const hipError_t e = launch_forward_kernel<T, N>(static_cast<const T*>(f), static_cast<cpx<T>*>(fhat),
+                                                   static_cast<cpx<T>*>(scratch), int(cells), st);
   prof_mark(kProfForward, false, st);
-  return hipGetLastError();
+  return e;
 }
 
 template <typename T, int N>

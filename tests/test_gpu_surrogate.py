@@ -124,7 +124,7 @@ def test_infer_indicator_and_fallback():
     n, L, cells = 16, 8.0, 200
     f = perturbed_maxwellians(n, L, cells, seed=3)
     plan = fks.Plan(n=n, L=L, R=6.0, a1=4, a2=4, dtype="f32", max_cells=64)
-    sur = fks.Surrogate(n=n, modes=8, width=128, max_batch=128)
+    sur = fks.Surrogate(n=n, modes=8, width=128, max_batch=256)
     sur.set_params(mlp.init_params([sur.n_in, 128, 128, sur.n_out], 9))
     fd = torch.as_tensor(f, dtype=torch.float32).cuda().contiguous()
     q_spec = plan.collide(fd)

@@ -38,3 +38,36 @@ def test_adam_first_step_is_sign_times_lr():
     opt = mlp.Adam(p, lr=0.01, eps=1e-12)
     out = opt.step(p, g)[0]
     np.testing.assert_allclose(out, p[0] - 0.01 * np.sign(g[0]), rtol=0, atol=1e-9)
+
+
+def test_features_of_a_maxwellian_match_its_fourier_transform():
+    # the coefficients of a Gaussian sampled on a wide, fine grid are its continuous
+    # Fourier transform: fhat_k / fhat_0 = exp(-i xi.u - T |xi|^2 / 2); the sampling
+    # (Poisson summation) error is ~2 exp(-2 pi^2 T / dv^2) = 1e-31 at dv = 0.5, T = 0.9
+    import fks_inputs
+    n, L, m = 32, 8.0, 8
+    rho, u, T = 1.3, np.array([0.4, -0.7, 0.2]), 0.9
+    f = fks_inputs.maxwellian_on_grid(n, L, [rho], [u], [T])[0]
+    x, r = mlp.features(f, L, m)
+    k = np.arange(-m // 2, m // 2)
+    KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
+    xi = np.pi / L * np.stack([KX, KY, KZ], -1)
+    expect = np.exp(-1j * (xi @ u) - 0.5 * T * np.sum(xi ** 2, -1)).ravel()
+    assert abs(r - rho) <= 1e-12
+    np.testing.assert_allclose(x[0::2], expect.real, atol=1e-12)
+    np.testing.assert_allclose(x[1::2], expect.imag, atol=1e-12)
+
+
+def test_moment_indicator_special_cases():
+    from oracle.conserve import project
+    from oracle.grid import make_grid
+    n, L = 8, 4.0
+    rng = np.random.default_rng(3)
+    q = rng.standard_normal((n, n, n))
+    # a constant has mass only: |sum q| = sum |q|
+    assert abs(mlp.moment_indicator(np.ones((n, n, n)), L) - 1.0) <= 1e-15
+    # after the conservation projection every invariant moment vanishes
+    qp = project(q, make_grid(n, L))
+    assert mlp.moment_indicator(qp, L) <= 1e-13
+    # the indicator is scale invariant
+    assert abs(mlp.moment_indicator(3.7 * q, L) - mlp.moment_indicator(q, L)) <= 1e-15
