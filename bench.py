@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "0f495a90a493ba6e", "bytes": 2064841104}
+SLAB_TRAFFIC = {"sha": "cf6e58257310895e", "bytes": 2128118914}
 
 
 def kernel_sources_hash():
