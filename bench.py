@@ -133,6 +133,7 @@ def bench_bkw(fks, torch, dev, steps=100, dt=0.01):
     plan = fks.Plan(n, L, R, kernel="vhs", alpha=0.0, C=1.0 / (4.0 * np.pi), a1=2, a2=3, n_radial=8,
                     dtype="f64", max_cells=1)
     f0 = torch.tensor(fks_inputs.bkw_initial(n, L, t0)[None], device=dev)
+    plan.autotune(f0, torch.empty_like(f0))        # one cell: the multi-slab schedule wins
     f = f0.clone()
     tmp = (torch.empty_like(f), torch.empty_like(f))
     s = torch.cuda.Stream()
@@ -156,7 +157,95 @@ def bench_bkw(fks, torch, dev, steps=100, dt=0.01):
     return {"workload": "BKW, Maxwell molecules, n=16, 6 directions x 8 radial nodes (48 terms), FP64, "
                         "100 Heun steps (200 Q evaluations) in one hipGraph",
             "ms_total": round(wall * 1e3, 3), "us_per_q": round(wall * 1e6 / (2 * steps), 2),
+            "schedule": plan.schedule(),
             "rel_l2_vs_closed_form": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+
+
+def bench_surrogate(fks, torch, dev, train_seconds=45.0, infer_cells=32768, threshold=1e-3):
+    """Fourier-mode MLP surrogate at n = 32 (1024 low-mode features -> 1024 -> 1024 ->
+    32768 outputs, BF16 MFMA, FP32 accumulation, Adam), trained online on fresh perturbed
+    Maxwellians (seed 1 family) labelled by the FP32 spectral path, within a time budget;
+    then Q for 32768 test cells (seed 3): surrogate only, and hybrid with the spectral
+    fallback where the moment indicator exceeds the threshold."""
+    import fks_inputs
+    from oracle import mlp
+    plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=4096)
+    width, batch, chunk = 1024, 512, 8192
+    sur = fks.Surrogate(n=N, modes=8, width=width, max_batch=4096, out_scale=3e-3)
+    sur.set_params(mlp.init_params([sur.n_in, width, width, sur.n_out], 1))
+    lr0 = 1e-3
+    t_start = time.perf_counter()
+    steps, samples, rnd, last_loss = 0, 0, 0, None
+    while True:
+        f = fks_inputs.perturbed_maxwellians_device(N, L, chunk, seed=10_000 + rnd, device=dev)
+        x, rho = sur.features(plan, f)
+        q = plan.collide(f)
+        t = sur.targets(q.reshape(chunk, -1), rho, t=q.reshape(chunk, -1))
+        del f
+        rnd += 1
+        for j in range(0, chunk, batch):
+            frac = min(1.0, (time.perf_counter() - t_start) / train_seconds)
+            lr = lr0 * 0.5 * (1.0 + np.cos(np.pi * frac))
+            loss = sur.train_step(x[j:j + batch], t[j:j + batch], lr=lr)
+            steps += 1
+            samples += batch
+        del x, t, q
+        torch.cuda.synchronize()
+        if time.perf_counter() - t_start >= train_seconds:
+            last_loss = loss.item()
+            break
+    train_wall = time.perf_counter() - t_start
+    # test cells
+    f = fks_inputs.perturbed_maxwellians_device(N, L, infer_cells, seed=3, device=dev)
+    q_spec = torch.empty_like(f)
+    for c0 in range(0, infer_cells, 4096):
+        plan.collide(f[c0:c0 + 4096], q_spec[c0:c0 + 4096])
+    r = torch.empty(infer_cells, dtype=torch.float64, device=dev)
+    q_sur, _ = sur.infer(plan, f, threshold=-1.0, indicator=r)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q_sur, _ = sur.infer(plan, f, q=q_sur, threshold=-1.0, indicator=r)
+    torch.cuda.synchronize()
+    w_sur = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q_h, n_fb = sur.infer(plan, f, threshold=threshold)
+    torch.cuda.synchronize()
+    w_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for c0 in range(0, infer_cells, 4096):
+        plan.collide(f[c0:c0 + 4096], q_spec[c0:c0 + 4096])
+    torch.cuda.synchronize()
+    w_spec = time.perf_counter() - t0
+
+    def err(a):
+        d = (a - q_spec).double().flatten(1)
+        qn = q_spec.double().flatten(1)
+        per = (d.norm(dim=1) / qn.norm(dim=1)).cpu().numpy()
+        return float(d.norm() / qn.norm()), float(np.median(per))
+
+    e_sur, m_sur = err(q_sur)
+    e_h, m_h = err(q_h)
+    work = infer_cells * N ** 3
+    # trade-off from the measured pieces: accepting the cells with r <= thr gives this
+    # error against the spectral Q and about this time (surrogate + fallback share)
+    d2 = (q_sur - q_spec).double().flatten(1).pow(2).sum(dim=1)
+    q2 = q_spec.double().flatten(1).pow(2).sum()
+    tradeoff = []
+    for thr in (1e-3, 3e-3, 1e-2, 3e-2, 1e-1):
+        acc = r <= thr
+        fb = 1.0 - float(acc.double().mean())
+        tradeoff.append({"threshold": thr, "fallback_frac": round(fb, 4),
+                         "rel_l2": float((d2[acc].sum() / q2).sqrt()),
+                         "est_value": round(work / (w_sur + fb * w_spec), 1)})
+    return {"workload": f"surrogate n=32, 8^3 modes -> 1024 -> 1024 -> 32768 (BF16 MFMA), online training on "
+                        f"perturbed Maxwellians labelled by the FP32 spectral path; test {infer_cells} cells (seed 3)",
+            "train": {"seconds": round(train_wall, 1), "steps": steps, "samples": samples, "final_loss": last_loss},
+            "surrogate_only": {"value": round(work / w_sur, 1), "ms": round(w_sur * 1e3, 3),
+                               "rel_l2_vs_spectral": e_sur, "median_cell_rel_l2": m_sur},
+            "hybrid": {"threshold": threshold, "fallback_cells": int(n_fb), "value": round(work / w_h, 1),
+                       "ms": round(w_h * 1e3, 3), "rel_l2_vs_spectral": e_h, "median_cell_rel_l2": m_h},
+            "spectral_only": {"value": round(work / w_spec, 1), "ms": round(w_spec * 1e3, 3)},
+            "tradeoff": tradeoff, "unit": "cells*N^3/s"}
 
 
 def bench_fks_step(fks, torch, dev, steps=20):
@@ -198,6 +287,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the uneven-batch, box-step and surrogate workloads")
+    ap.add_argument("--sur-train-seconds", type=float, default=45.0,
+                    help="training budget of the surrogate workload (online data)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default slab schedule (profiling runs: no extra dispatches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -299,6 +390,7 @@ def main():
         out["bkw_maxwell"] = bench_bkw(fks, torch, dev)
         out["uneven_batch"] = bench_uneven(fks, torch, dev)
         out["fks_step_box"] = bench_fks_step(fks, torch, dev)
+        out["surrogate"] = bench_surrogate(fks, torch, dev, train_seconds=args.sur_train_seconds)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -39,8 +39,10 @@ struct Variants<float, N> {
 };
 template <int N>
 struct Variants<double, N> {
-  static constexpr int count = 1;
-  static constexpr int s[2] = {N >= 32 ? 8 : (N >= 24 ? 4 : 1), 0};
+  // n = 16 also has a 6-slab schedule: six workgroups per cell cut the latency of small
+  // batches (a single space-homogeneous cell)
+  static constexpr int count = (N == 16) ? 2 : 1;
+  static constexpr int s[2] = {N >= 32 ? 8 : (N >= 24 ? 4 : 1), N == 16 ? 6 : 0};
 };
 
 // Grid constants shared by all schedules of (precision, n).

@@ -182,11 +182,11 @@ def test_full_batch_4096_sampled():
     assert np.median(mass) <= 1e-6 and mass.max() <= 1e-4
 
 
-@pytest.mark.parametrize("n", [16, 24, 32])
-def test_every_schedule_matches_oracle(n):
-    plan = gpu_plan(n, "f32", max_cells=8)
+@pytest.mark.parametrize("n,dtype", [(16, "f32"), (24, "f32"), (32, "f32"), (16, "f64"), (24, "f64")])
+def test_every_schedule_matches_oracle(n, dtype):
+    plan = gpu_plan(n, dtype, max_cells=8)
     f = fks_inputs.maxwellian_mixture(n, 8.0, 8, seed=300 + n)
-    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ft = torch.tensor(f, dtype=torch.float32 if dtype == "f32" else torch.float64, device="cuda")
     ref, _ = oracle_q(ft.double().cpu().numpy(), n)
     from paper_1701_01608_amd import _lib
     import ctypes
@@ -200,8 +200,8 @@ def test_every_schedule_matches_oracle(n):
             q = plan.collide(ft)
             torch.cuda.synchronize()
             err = rel(q.double().cpu().numpy(), ref)
-            print(f"n={n} slabs={slabs} xcd={xcd} rel-L2 {err:.2e}", flush=True)
-            assert err <= TOL["f32"]
+            print(f"n={n} {dtype} slabs={slabs} xcd={xcd} rel-L2 {err:.2e}", flush=True)
+            assert err <= TOL[dtype]
     assert seen >= 2
 
 
