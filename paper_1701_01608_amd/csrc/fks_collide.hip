@@ -73,11 +73,15 @@ struct Cfg : Grid<T, N> {
   static constexpr int LINES = Z * P;  // x lines (z', y) of the slab
   static constexpr int NCH = (N + Z - 1) / Z;  // k_z chunks of the fold period Z
   static constexpr int NT = GREG ? ((2 * LINES + 63) / 64) * 64 : 256;
-  static constexpr size_t w_bytes = size_t(Z) * K * WS * sizeof(cpx<T>);
+  static constexpr size_t w_elems = size_t(Z) * K * WS;
+  static constexpr size_t w_bytes = w_elems * sizeof(cpx<T>);
+  // FP32: stage 1's output buffer [Z][K][K] beside W (double buffering across terms)
+  static constexpr size_t x_bytes = GREG ? size_t(Z) * K * K * sizeof(cpx<T>) : 0;
   // after the last term: G staged as [LINES][P] reals, then its x spectra [Z][KH1][WS]
   static constexpr size_t gst_bytes = GREG ? ((size_t(LINES) * P * sizeof(T) + 255) / 256) * 256 : 0;
   static constexpr size_t spec_bytes = size_t(Z) * KH1 * WS * sizeof(cpx<T>);
-  static constexpr size_t lds_bytes = (w_bytes > gst_bytes + spec_bytes) ? w_bytes : gst_bytes + spec_bytes;
+  static constexpr size_t lds_bytes =
+      (w_bytes + x_bytes > gst_bytes + spec_bytes) ? w_bytes + x_bytes : gst_bytes + spec_bytes;
   static_assert(P % S == 0, "slab count must divide P");
   static_assert(P % 2 == 0, "half lines need an even P");
   static_assert(NCH * Z <= NRL, "layout rows too few for this schedule");
@@ -282,18 +286,20 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   constexpr uint32_t row_bytes = uint32_t(NPAIR) * sizeof(cpx<T>);  // one k_z row, fhat and tables
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(fh, uint32_t(C::NRL) * row_bytes);
   const __amdgpu_buffer_rsrc_t rt = make_rsrc(tab, uint32_t(n_terms) * C::NRL * row_bytes);
-  for (int t = 0; t < n_terms; ++t) {
+  // stage 1 of term t: half-plane pencil p and its mirror.  Mode k_z of pencil (kx, ky)
+  // and mode -k_z of (-kx, -ky) come from the same stored value (Hermitian fhat, even
+  // tables).  Rows are taken in chunks j of Z consecutive modes; with k_z = jZ + b - N/2
+  // the slab twiddle exp(2 pi i k_z r/P) = w_S^{jr} exp(2 pi i (b - N/2) r/P): the chunk
+  // factor is one runtime scalar, the per-bin factor is applied once after the loop.
+  // Output: the Z planes [z'][kx + Kh][ky + Kh] of dst with row stride `ld`.
+  auto stage1 = [&](int t, cpx<T>* dst, auto ld_c) {
+    constexpr int LD = decltype(ld_c)::value;
     const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
     // Every stage takes an opaque copy of the thread index (opaque_tid): its index
     // arithmetic is redone where it is used instead of being hoisted out of the term
     // loop or shared between stages and kept live next to the accumulator (LDS plane
     // offsets beyond the 64 KiB immediate range need their own address registers).
-    int tid = opaque_tid();
-    // stage 1: half-plane pencil p and its mirror.  Mode k_z of pencil (kx, ky) and mode
-    // -k_z of (-kx, -ky) come from the same stored value (Hermitian fhat, even tables).
-    // Rows are taken in chunks j of Z consecutive modes; with k_z = jZ + b - N/2 the
-    // slab twiddle exp(2 pi i k_z r/P) = w_S^{jr} exp(2 pi i (b - N/2) r/P): the chunk
-    // factor is one runtime scalar, the per-bin factor is applied once after the loop.
+    const int tid = opaque_tid();
     for (int p = tid; p < NPAIR; p += NT) {
       int kx, ky;
       pair_kxy<K, Kh>(p, kx, ky);
@@ -353,75 +359,95 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
       });
       dft<Z, +1>(oA);
       const int kxa = kx + Kh, kya = ky + Kh;
-      static_for<0, Z>([&](auto zp) { W[(size_t(zp) * K + kxa) * WS + kya] = oA[zp]; });
+      static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxa) * LD + kya] = oA[zp]; });
       if (kx != 0 || ky != 0) {
         dft<Z, +1>(oB);
         const int kxb = Kh - kx, kyb = Kh - ky;
-        static_for<0, Z>([&](auto zp) { W[(size_t(zp) * K + kxb) * WS + kyb] = oB[zp]; });
+        static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxb) * LD + kyb] = oB[zp]; });
       }
     }
+  };
+
+  if constexpr (C::GREG) {
+    // FP32: two LDS buffers.  X holds stage 1's output [Z][K][K]; W the y-transformed
+    // planes [Z][K][P+1].  Per term t: stage 2 reads X(t) and writes W; then, in one
+    // barrier interval, stage 1 of term t+1 refills X while stage 3 of term t consumes W,
+    // so the waves waiting on stage 1's loads overlap with the others' x-line transforms.
+    cpx<T>* X = W + C::w_elems;
+    using LdX = std::integral_constant<int, K>;
+    stage1(0, X, LdX{});
     __syncthreads();
-    // stage 2: y lines (z', kx): K modes -> P points, in place
-    tid = opaque_tid();
-    if constexpr (C::GREG) {
-      // half lines: work item it = h*Z*K + line computes the outputs y = 2j + h of one
-      // line; all inputs of a round are read before any output of that round is written
-      constexpr int HL = Z * K, ITEMS = 2 * HL, ROUNDS = (ITEMS + NT - 1) / NT;
-      for (int rd = 0; rd < ROUNDS; ++rd) {
-        const int it = rd * NT + tid;
-        const bool act = it < ITEMS;
-        const int h = act ? it / HL : 0;
-        cpx<T>* row = W + size_t(act ? it - h * HL : 0) * WS;
-        cpx<T> u[P / 2];
-        if (h) {
-          if (act) fold_half<P, Kh, 1>(u, [&](int i) { return row[i]; });
-        } else {
-          if (act) fold_half<P, Kh, 0>(u, [&](int i) { return row[i]; });
-        }
-        __syncthreads();
-        if (act) {
+    for (int t = 0; t < n_terms; ++t) {
+      // stage 2: y lines (z', kx): K modes -> P points; work item it = h*Z*K + line
+      // computes the outputs y = 2j + h of one line
+      {
+        const int tid = opaque_tid();
+        constexpr int HL = Z * K, ITEMS = 2 * HL;
+        static_assert(ITEMS <= NT, "one round of half lines");
+        if (tid < ITEMS) {
+          const int h = tid / HL, line = tid - h * HL;
+          const cpx<T>* src = X + size_t(line) * K;
+          cpx<T>* row = W + size_t(line) * WS;
+          cpx<T> u[P / 2];
+          if (h) fold_half<P, Kh, 1>(u, [&](int i) { return src[i]; });
+          else fold_half<P, Kh, 0>(u, [&](int i) { return src[i]; });
           dft<P / 2, +1>(u);
           static_for<0, P / 2>([&](auto j) { row[2 * decltype(j)::value + h] = u[j]; });
         }
       }
-    } else {
-      for (int it = tid; it < Z * K; it += NT) {
-        cpx<T>* row = W + size_t(it) * WS;
-        cpx<T> a[P];
-        static_for<0, P>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
-        static_for<0, K>([&](auto kyi) { a[(decltype(kyi)::value - Kh + P) % P] = row[kyi]; });
-        dft<P, +1>(a);
-        static_for<0, P>([&](auto y) { row[y] = a[y]; });
+      __syncthreads();
+      if (t + 1 < n_terms) stage1(t + 1, X, LdX{});
+      // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
+      {
+        const int tid = opaque_tid();
+        if (tid < 2 * C::LINES) {
+          const int h = tid / C::LINES, line = tid - h * C::LINES;
+          const int zp = line / P, y = line % P;
+          const cpx<T>* col = W + size_t(zp) * K * WS + y;
+          cpx<T> u[P / 2];
+          if (h) fold_half<P, Kh, 1>(u, [&](int i) { return col[size_t(i) * WS]; });
+          else fold_half<P, Kh, 0>(u, [&](int i) { return col[size_t(i) * WS]; });
+          dft<P / 2, +1>(u);
+          static_for<0, P / 2>([&](auto j) { g[j] += u[j].re * u[j].im; });
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
-    tid = opaque_tid();
-    if constexpr (C::GREG) {
-      if (tid < 2 * C::LINES) {
-        const int h = tid / C::LINES, line = tid - h * C::LINES;
-        const int zp = line / P, y = line % P;
-        const cpx<T>* col = W + size_t(zp) * K * WS + y;
-        cpx<T> u[P / 2];
-        if (h) fold_half<P, Kh, 1>(u, [&](int i) { return col[size_t(i) * WS]; });
-        else fold_half<P, Kh, 0>(u, [&](int i) { return col[size_t(i) * WS]; });
-        dft<P / 2, +1>(u);
-        static_for<0, P / 2>([&](auto j) { g[j] += u[j].re * u[j].im; });
+  } else {
+    using LdW = std::integral_constant<int, WS>;
+    for (int t = 0; t < n_terms; ++t) {
+      stage1(t, W, LdW{});
+      __syncthreads();
+      // stage 2: y lines (z', kx): K modes -> P points, in place
+      {
+        const int tid = opaque_tid();
+        for (int it = tid; it < Z * K; it += NT) {
+          cpx<T>* row = W + size_t(it) * WS;
+          cpx<T> a[P];
+          static_for<0, P>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
+          static_for<0, K>([&](auto kyi) { a[(decltype(kyi)::value - Kh + P) % P] = row[kyi]; });
+          dft<P, +1>(a);
+          static_for<0, P>([&](auto y) { row[y] = a[y]; });
+        }
       }
-    } else {
-      for (int it = tid; it < Z * P; it += NT) {
-        const int zp = it / P, y = it % P;
-        cpx<T> a[P];
-        static_for<0, P>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
-        static_for<0, K>([&](auto kxi) {
-          a[(decltype(kxi)::value - Kh + P) % P] = W[(size_t(zp) * K + kxi) * WS + y];
-        });
-        dft<P, +1>(a);
-        T* gl = Gw + size_t(it) * P;
-        static_for<0, P>([&](auto x) { gl[x] += a[x].re * a[x].im; });
+      __syncthreads();
+      // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
+      {
+        const int tid = opaque_tid();
+        for (int it = tid; it < Z * P; it += NT) {
+          const int zp = it / P, y = it % P;
+          cpx<T> a[P];
+          static_for<0, P>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
+          static_for<0, K>([&](auto kxi) {
+            a[(decltype(kxi)::value - Kh + P) % P] = W[(size_t(zp) * K + kxi) * WS + y];
+          });
+          dft<P, +1>(a);
+          T* gl = Gw + size_t(it) * P;
+          static_for<0, P>([&](auto x) { gl[x] += a[x].re * a[x].im; });
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // forward x pass: real G lines (z', y) -> kx in [0, Kh] -> W[z'][kx][y]
