@@ -303,10 +303,16 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     for (int p = tid; p < NPAIR; p += NT) {
       int kx, ky;
       pair_kxy<K, Kh>(p, kx, ky);
-      cpx<T> bA[Z], bB[Z];
+      // With g = w f (w the chunk twiddle) and the real table pair (a, b), the pencil
+      // accumulates (a + ib) g and its mirror conj((a - ib) g); both come from the four
+      // real sums s1 = sum a Re g, s2 = sum b Im g, s3 = sum a Im g, s4 = sum b Re g:
+      // A = (s1 - s2, s3 + s4), B = (s1 + s2, s4 - s3).
+      T s1[Z], s2[Z], s3[Z], s4[Z];
       static_for<0, Z>([&](auto bb) {
-        bA[bb] = cpx<T>{T(0), T(0)};
-        bB[bb] = cpx<T>{T(0), T(0)};
+        s1[bb] = T(0);
+        s2[bb] = T(0);
+        s3[bb] = T(0);
+        s4[bb] = T(0);
       });
       const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
       // software pipeline over half chunks: the loads of the next half chunk are in
@@ -330,11 +336,11 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
           constexpr int bb = b0 + decltype(i)::value;
           if constexpr (bb < Z) {
             const cpx<T> fv = pf[i], ab = pa[i];
-            const T ar = ab.re * fv.re, ai = ab.re * fv.im, br = ab.im * fv.re, bi = ab.im * fv.im;
-            const cpx<T> cA = {ar - bi, ai + br};   // (a + ib) fv
-            const cpx<T> cB = {ar + bi, br - ai};   // (a + ib) conj(fv)
-            bA[bb] = bA[bb] + cpx<T>{cr * cA.re - ci * cA.im, cr * cA.im + ci * cA.re};
-            bB[bb] = bB[bb] + cpx<T>{cr * cB.re + ci * cB.im, cr * cB.im - ci * cB.re};
+            const T gr = cr * fv.re - ci * fv.im, gi = cr * fv.im + ci * fv.re;
+            s1[bb] += ab.re * gr;
+            s2[bb] += ab.im * gi;
+            s3[bb] += ab.re * gi;
+            s4[bb] += ab.im * gr;
           }
         });
       };
@@ -354,8 +360,10 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
       cpx<T> oA[Z], oB[Z];
       static_for<0, Z>([&](auto bb) {
         constexpr int e = decltype(bb)::value - N / 2;
-        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA[bb]);
-        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB[bb]);
+        const cpx<T> bA = {s1[bb] - s2[bb], s3[bb] + s4[bb]};
+        const cpx<T> bB = {s1[bb] + s2[bb], s4[bb] - s3[bb]};
+        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA);
+        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB);
       });
       dft<Z, +1>(oA);
       const int kxa = kx + Kh, kya = ky + Kh;
