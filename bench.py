@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "cf6e58257310895e", "bytes": 2128118914}
+SLAB_TRAFFIC = {"sha": "19057c3d816b0f47", "bytes": 2247749632}
 
 
 def kernel_sources_hash():
@@ -161,7 +161,7 @@ def bench_bkw(fks, torch, dev, steps=100, dt=0.01):
             "rel_l2_vs_closed_form": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
 
 
-def bench_surrogate(fks, torch, dev, train_seconds=45.0, infer_cells=32768, threshold=1e-3):
+def bench_surrogate(fks, torch, dev, train_seconds=60.0, infer_cells=32768, threshold=1e-3):
     """Fourier-mode MLP surrogate at n = 32 (1024 low-mode features -> 1024 -> 1024 ->
     32768 outputs, BF16 MFMA, FP32 accumulation, Adam), trained online on fresh perturbed
     Maxwellians (seed 1 family) labelled by the FP32 spectral path, within a time budget;
@@ -170,10 +170,10 @@ def bench_surrogate(fks, torch, dev, train_seconds=45.0, infer_cells=32768, thre
     import fks_inputs
     from oracle import mlp
     plan = fks.Plan(N, L, R, a1=A1, a2=A2, C=0.25, dtype="f32", max_cells=4096)
-    width, batch, chunk = 1024, 512, 8192
+    width, batch, chunk = 1024, 1024, 8192
     sur = fks.Surrogate(n=N, modes=8, width=width, max_batch=4096, out_scale=3e-3)
     sur.set_params(mlp.init_params([sur.n_in, width, width, sur.n_out], 1))
-    lr0 = 1e-3
+    lr0 = 2e-3
     t_start = time.perf_counter()
     steps, samples, rnd, last_loss = 0, 0, 0, None
     while True:
@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the uneven-batch, box-step and surrogate workloads")
-    ap.add_argument("--sur-train-seconds", type=float, default=45.0,
+    ap.add_argument("--sur-train-seconds", type=float, default=60.0,
                     help="training budget of the surrogate workload (online data)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default slab schedule (profiling runs: no extra dispatches)")
