@@ -202,9 +202,14 @@ void fks_xport_destroy(fks_xport xp);
  * copies) and a workspace (activations), both caller-owned, 256-byte aligned. */
 typedef struct fks_sur_s* fks_sur;
 /* out_scale > 0 fixes the output units: Q = out_scale rho^2 y (choose it near the
- * typical size of Q / rho^2 so that the network's outputs are of order one). */
+ * typical size of Q / rho^2 so that the network's outputs are of order one).
+ * flags FKS_SUR_CENTER: the network works in each cell's mean-velocity frame u (from
+ * the FP64 moments of f): features are the coefficients of f(v + u) (fhat_k e^{i xi_k.u}),
+ * targets are Q(v + u) / (s rho^2), and predictions are shifted back by the same exact
+ * spectral shift (the spectral Q commutes with velocity shifts); n in {8, 16, 24, 32}. */
+#define FKS_SUR_CENTER 1u
 fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_batch, float out_scale,
-                          fks_sur* out);
+                          uint32_t flags, fks_sur* out);
 /* n_params = number of FP32 values of the host parameter vector */
 fks_status fks_sur_sizes(fks_sur s, size_t* param_bytes, size_t* workspace_bytes, int64_t* n_params);
 fks_status fks_sur_bind(fks_sur s, void* d_params, size_t param_bytes, void* d_workspace, size_t workspace_bytes,
@@ -215,12 +220,16 @@ fks_status fks_sur_set_params(fks_sur s, const float* host, void* stream);
  * FP32 values out; synchronises `stream`. */
 fks_status fks_sur_get(fks_sur s, int32_t which, float* host, void* stream);
 /* Features of n_cells distributions f (plan dtype, plan grid n == surrogate n):
- * x [n_cells][2 m^3] BF16 (device), rho [n_cells] FP32 (device).  Uses the plan's
- * workspace. */
-fks_status fks_sur_features(fks_sur s, fks_plan plan, const void* f, void* x, float* rho, int64_t n_cells,
-                            void* stream);
-/* Training targets t = q / (s rho^2) ([n_cells][n^3] FP32, device; t may equal q). */
-fks_status fks_sur_targets(fks_sur s, const float* q, const float* rho, float* t, int64_t n_cells, void* stream);
+ * x [n_cells][2 m^3] BF16 (device), rho [n_cells] FP32 (device), and, if mom != NULL,
+ * the FP64 moments sum phi f dv^3, phi = (1, v, |v|^2/2), [n_cells][5] (device; required
+ * for a centred surrogate).  Uses the plan's workspace. */
+fks_status fks_sur_features(fks_sur s, fks_plan plan, const void* f, void* x, float* rho, double* mom,
+                            int64_t n_cells, void* stream);
+/* Training targets t = q / (s rho^2) ([n_cells][n^3] FP32, device; t may equal q); for a
+ * centred surrogate t(v) = q(v + u) / (s rho^2) with u from mom (fks_sur_features).  The
+ * plan supplies the grid (n, L). */
+fks_status fks_sur_targets(fks_sur s, fks_plan plan, const float* q, const float* rho, const double* mom, float* t,
+                           int64_t n_cells, void* stream);
 /* y [batch][n^3] FP32 = network(x), x [batch][2 m^3] BF16, both device. */
 fks_status fks_sur_forward(fks_sur s, const void* x, float* y, int64_t batch, void* stream);
 /* One step on (x, t): forward, loss gradient into the gradient buffer, and, if

@@ -97,14 +97,44 @@ class Adam:
 
 
 # ---- surrogate inputs and checks -------------------------------------------------------
-def features(f, L, modes):
+def mean_velocity(f, L):
+    """u = sum v f / sum f on the velocity grid of f (n, n, n)."""
+    from .grid import make_grid
+    v = make_grid(f.shape[0], L).v
+    m = f.sum()
+    return np.array([np.tensordot(f.sum(axis=(1, 2)), v, 1), np.tensordot(f.sum(axis=(0, 2)), v, 1),
+                     np.tensordot(f.sum(axis=(0, 1)), v, 1)]) / m
+
+
+def spectral_shift(f, delta, L):
+    """g(v) = f(v + delta) for the Fourier interpolant of the grid samples f (n, n, n)
+    (the Nyquist modes dropped, as in the method's mode set), one axis after the other."""
+    n = f.shape[0]
+    k = np.arange(n // 2 + 1)
+    g = np.asarray(f, dtype=np.float64)
+    for ax in range(3):
+        F = np.fft.rfft(g, axis=ax)
+        ph = np.exp(1j * np.pi * k * delta[ax] / L)
+        ph[n // 2] = 0.0
+        shape = [1, 1, 1]
+        shape[ax] = n // 2 + 1
+        g = np.fft.irfft(F * ph.reshape(shape), n=n, axis=ax)
+    return g
+
+
+def features(f, L, modes, center=False):
     """Network input of one cell: Re, Im (interleaved) of fhat_k / fhat_0 for
     k in [-modes/2, modes/2 - 1]^3 (k_z fastest), fhat the Appendix A coefficients of
-    the grid samples f (n, n, n); and the density rho = (2L)^3 fhat_0."""
+    the grid samples f (n, n, n) (with center: of f(v + u), u the mean velocity, i.e.
+    fhat_k e^{i xi_k.u}); and the density rho = (2L)^3 fhat_0."""
     from .grid import fourier_coefficients, make_grid
     n = f.shape[0]
     g = make_grid(n, L)
     fh = fourier_coefficients(f, g)
+    if center:
+        u = mean_velocity(f, L)
+        X, Y, Z = np.meshgrid(g.xi, g.xi, g.xi, indexing="ij")
+        fh = fh * np.exp(1j * (X * u[0] + Y * u[1] + Z * u[2]))
     c = n // 2 - 1                       # index of k = 0
     mh = modes // 2
     sub = fh[c - mh:c + mh, c - mh:c + mh, c - mh:c + mh] / fh[c, c, c]

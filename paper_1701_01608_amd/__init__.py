@@ -143,12 +143,15 @@ class Surrogate:
     Parameters, Adam state and activations live in two device buffers allocated here and
     bound once; every computation runs in the library's kernels."""
 
-    def __init__(self, n, modes=8, width=1024, max_batch=1024, out_scale=1.0, device="cuda", stream=None):
+    def __init__(self, n, modes=8, width=1024, max_batch=1024, out_scale=1.0, center=False, device="cuda",
+                 stream=None):
         L_ = _lib.lib()
         h = ctypes.c_void_p()
-        _lib.check(L_.fks_sur_create(int(n), int(modes), int(width), int(max_batch), float(out_scale),
+        flags = _lib.FKS_SUR_CENTER if center else 0
+        _lib.check(L_.fks_sur_create(int(n), int(modes), int(width), int(max_batch), float(out_scale), flags,
                                      ctypes.byref(h)))
         self.out_scale = float(out_scale)
+        self.center = bool(center)
         self._h = h
         self.n, self.modes, self.width, self.max_batch = int(n), int(modes), int(width), int(max_batch)
         self.n_in, self.n_out = 2 * self.modes ** 3, self.n ** 3
@@ -191,23 +194,29 @@ class Surrogate:
     def get_grads(self, stream=None):
         return self._get(1, stream)
 
-    def features(self, plan, f, x=None, rho=None, stream=None):
+    def features(self, plan, f, x=None, rho=None, mom=None, stream=None):
+        """(x, rho, mom): BF16 features, FP32 densities and FP64 moments of f."""
         cells = plan._check_f(f)
         if x is None:
             x = torch.empty((cells, self.n_in), dtype=torch.bfloat16, device=f.device)
         if rho is None:
             rho = torch.empty(cells, dtype=torch.float32, device=f.device)
+        if mom is None:
+            mom = torch.empty((cells, 5), dtype=torch.float64, device=f.device)
         if not (x.dtype == torch.bfloat16 and x.is_contiguous() and x.numel() >= cells * self.n_in):
             raise FKSError(-1, "x must be a contiguous bfloat16 tensor of [cells, 2 modes^3]")
-        _lib.check(_lib.lib().fks_sur_features(self._h, plan.handle, _ptr(f), _ptr(x), _ptr(rho), cells,
+        if not (mom.dtype == torch.float64 and mom.is_contiguous() and mom.numel() >= 5 * cells):
+            raise FKSError(-1, "mom must be a contiguous float64 tensor of [cells, 5]")
+        _lib.check(_lib.lib().fks_sur_features(self._h, plan.handle, _ptr(f), _ptr(x), _ptr(rho), _ptr(mom), cells,
                                                _stream_ptr(stream)))
-        return x, rho
+        return x, rho, mom
 
-    def targets(self, q, rho, t=None, stream=None):
+    def targets(self, plan, q, rho, mom=None, t=None, stream=None):
         cells = q.numel() // self.n_out
         if t is None:
             t = torch.empty_like(q)
-        _lib.check(_lib.lib().fks_sur_targets(self._h, _ptr(q), _ptr(rho), _ptr(t), cells, _stream_ptr(stream)))
+        _lib.check(_lib.lib().fks_sur_targets(self._h, plan.handle, _ptr(q), _ptr(rho), _ptr(mom), _ptr(t), cells,
+                                              _stream_ptr(stream)))
         return t
 
     def forward(self, x, y=None, stream=None):

@@ -12,6 +12,7 @@ FKS_F64 = 0
 FKS_F32 = 1
 FKS_CONSERVE = 1
 FKS_ALLOW_OVERLAP = 2
+FKS_SUR_CENTER = 1
 
 STATUS = {0: "FKS_OK", -1: "FKS_E_ARG", -2: "FKS_E_UNSUPPORTED", -3: "FKS_E_WORKSPACE",
           -4: "FKS_E_DEVICE", -5: "FKS_E_STATE"}
@@ -67,14 +68,14 @@ _SIGS = {
     "fks_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, _VP, _VP]),
     "fks_xport_destroy": (None, [_VP]),
     "fks_sur_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                      ctypes.c_float, ctypes.POINTER(_VP)]),
+                                      ctypes.c_float, ctypes.c_uint32, ctypes.POINTER(_VP)]),
     "fks_sur_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                      ctypes.POINTER(ctypes.c_int64)]),
     "fks_sur_bind": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.c_size_t, _VP]),
     "fks_sur_set_params": (ctypes.c_int, [_VP, _VP, _VP]),
     "fks_sur_get": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
-    "fks_sur_features": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
-    "fks_sur_targets": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_sur_features": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_sur_targets": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fks_sur_forward": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fks_sur_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _VP,
                                           _VP]),

@@ -165,6 +165,7 @@ struct fks_plan_s {
 struct fks_sur_s {
   int n = 0, modes = 0, width = 0;
   float scale = 1.0f;  // Q = scale * rho^2 * y
+  bool center = false; // network works in each cell's mean-velocity frame
   int64_t max_batch = 0;
   int fin = 0, fout = 0;  // features 2*modes^3, outputs n^3
   size_t n_params = 0;
@@ -176,8 +177,9 @@ struct fks_sur_s {
   size_t p_master = 0, p_m = 0, p_v = 0, p_g = 0, p_w16 = 0;
   // workspace carve-up (bytes)
   size_t w_z1 = 0, w_z2 = 0, w_h1 = 0, w_h2 = 0, w_y = 0, w_dy = 0, w_dz1 = 0, w_dz2 = 0, w_part = 0, w_rho = 0,
-         w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0;
-  int part_blocks = 256;
+         w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0, w_cs = 0, w_sk = 0, w_mom = 0;
+  int part_blocks = 1024;
+  int splits = 1;  // split K of the output layer's input gradient (K = n^3)
   int64_t adam_t = 0;
   bool bound = false;
 };
@@ -757,6 +759,8 @@ uint16_t bf16_bits(float x) {
   return uint16_t(u >> 16);
 }
 
+constexpr int kColsumBlocks = 32;  // row blocks of the two-pass bias-gradient sums
+
 fks_status sur_ready(const fks_sur_s* s) {
   if (!s) return fail(FKS_E_ARG, "null surrogate");
   if (!s->bound) return fail(FKS_E_STATE, "surrogate buffers not bound (call fks_sur_bind)");
@@ -803,18 +807,22 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
   st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, dy, B(s->d_ws, s->w_h2), fo, w, r, fo, w, nullptr,
                                   G + s->off_w[2], nullptr, nullptr, w, stream),
                  "dW3");
-  if (st == FKS_OK) st = check_hip(fks::launch_colsum(dy, r, fo, G + s->off_b[2], stream), "db3");
+  float* cs = reinterpret_cast<float*>(B(s->d_ws, s->w_cs));
+  if (st == FKS_OK) st = check_hip(fks::launch_colsum(dy, r, fo, G + s->off_b[2], cs, kColsumBlocks, stream), "db3");
+  // dZ2: K = n^3 is long and M x N = batch x width has few tiles: split K
   if (st == FKS_OK)
-    st = check_hip(fks::launch_gemm(0, 1, fks::kEpiDSilu_, dy, W16 + 2 * s->off_w[2], r, w, fo, fo, w, nullptr,
-                                    nullptr, B(s->d_ws, s->w_dz2),
-                                    reinterpret_cast<const float*>(B(s->d_ws, s->w_z2)), w, stream),
+    st = check_hip(fks::launch_gemm_dsilu_splitk(dy, W16 + 2 * s->off_w[2], r, w, fo, fo, w,
+                                                 reinterpret_cast<const float*>(B(s->d_ws, s->w_z2)),
+                                                 B(s->d_ws, s->w_dz2), s->splits,
+                                                 reinterpret_cast<float*>(B(s->d_ws, s->w_sk)), stream),
                    "dZ2");
   // layer 2
   if (st == FKS_OK)
     st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz2), B(s->d_ws, s->w_h1), w, w, r, w, w,
                                     nullptr, G + s->off_w[1], nullptr, nullptr, w, stream),
                    "dW2");
-  if (st == FKS_OK) st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz2), r, w, G + s->off_b[1], stream), "db2");
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz2), r, w, G + s->off_b[1], cs, kColsumBlocks, stream), "db2");
   if (st == FKS_OK)
     st = check_hip(fks::launch_gemm(0, 1, fks::kEpiDSilu_, B(s->d_ws, s->w_dz2), W16 + 2 * s->off_w[1], r, w, w, w, w,
                                     nullptr, nullptr, B(s->d_ws, s->w_dz1),
@@ -825,14 +833,19 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
     st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz1), x, w, fi, r, w, fi, nullptr,
                                     G + s->off_w[0], nullptr, nullptr, fi, stream),
                    "dW1");
-  if (st == FKS_OK) st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz1), r, w, G + s->off_b[0], stream), "db1");
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz1), r, w, G + s->off_b[0], cs, kColsumBlocks, stream), "db1");
   return st;
 }
 }  // namespace
 
-fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_batch, float out_scale, fks_sur* out) {
+fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_batch, float out_scale, uint32_t flags,
+                          fks_sur* out) {
   if (!out) return fail(FKS_E_ARG, "null out");
   *out = nullptr;
+  if (flags & ~uint32_t(FKS_SUR_CENTER)) return fail(FKS_E_ARG, "unknown flags");
+  if ((flags & FKS_SUR_CENTER) && n != 8 && n != 16 && n != 24 && n != 32)
+    return fail(FKS_E_UNSUPPORTED, "centring is built for n = 8, 16, 24, 32");
   if (!(out_scale > 0.0f) || !std::isfinite(out_scale)) return fail(FKS_E_ARG, "out_scale must be positive");
   if (n < 4 || n > 64) return fail(FKS_E_ARG, "n out of range");
   if (modes < 2 || modes % 2 || modes > n - 2) return fail(FKS_E_ARG, "modes must be even and <= n - 2");
@@ -845,6 +858,7 @@ fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_b
   if (!s) return fail(FKS_E_ARG, "out of host memory");
   s->n = n;
   s->scale = out_scale;
+  s->center = (flags & FKS_SUR_CENTER) != 0;
   s->modes = modes;
   s->width = width;
   s->max_batch = max_batch;
@@ -884,6 +898,16 @@ fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_b
   s->w_x = wb;    wb = round256(wb + 2 * Bm * fi);
   s->w_gf = wb;   wb = round256(wb + 4 * Bm * fo);  // fallback gather buffers (FP32 cells)
   s->w_gq = wb;   wb = round256(wb + 4 * Bm * fo);
+  s->w_cs = wb;   wb = round256(wb + 4 * size_t(kColsumBlocks) * (fo > w ? fo : w));
+  s->w_mom = wb;  wb = round256(wb + 8 * 5 * Bm);
+  // largest split count <= 16 whose K range is a whole number of 32-wide GEMM k steps
+  s->splits = 1;
+  for (int sp = 16; sp > 1; --sp)
+    if (fo % (32 * size_t(sp)) == 0) {
+      s->splits = sp;
+      break;
+    }
+  s->w_sk = wb;   wb = round256(wb + 4 * size_t(s->splits) * Bm * w);
   s->ws_bytes = wb;
   *out = s;
   return ok();
@@ -942,13 +966,16 @@ fks_status fks_sur_get(fks_sur s, int32_t which, float* host, void* stream) {
   return st == FKS_OK ? ok() : st;
 }
 
-fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float* rho, int64_t n_cells, void* stream) {
+fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float* rho, double* mom, int64_t n_cells,
+                            void* stream) {
   fks_status st = sur_ready(s);
   if (st != FKS_OK) return st;
   st = check_plan_ready(p);
   if (st != FKS_OK) return st;
   if (p->n != s->n) return fail(FKS_E_ARG, "plan and surrogate grids differ");
   if (n_cells < 0 || (n_cells > 0 && (!f || !x || !rho))) return fail(FKS_E_ARG, "bad buffers");
+  if (s->center && n_cells > 0 && !mom) return fail(FKS_E_ARG, "a centred surrogate needs the moments buffer");
+  const double dv = 2.0 * p->d.L / p->n;
   const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
   const int f32 = p->d.dtype == FKS_F32;
   const double box3 = 8.0 * p->d.L * p->d.L * p->d.L;
@@ -959,23 +986,39 @@ fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float
                                        ws + p->off_fhat, ws + p->off_scr, c, stream),
                    "feature transform");
     if (st != FKS_OK) return st;
+    if (mom) {
+      st = check_hip(fks::launch_moments(f32, p->n, static_cast<const unsigned char*>(f) + size_t(c0) * cell_bytes, c,
+                                         mom + size_t(c0) * 5, p->d.L, dv, stream),
+                     "moments");
+      if (st != FKS_OK) return st;
+    }
     st = check_hip(fks::launch_lowmodes(f32, ws + p->off_fhat, p->geo.table_rows, p->n / 2, p->geo.npair, p->K, p->Kh,
                                         s->modes / 2, box3, static_cast<unsigned char*>(x) + size_t(c0) * 2 * s->fin,
-                                        s->fin, rho + c0, c, stream),
+                                        s->fin, rho + c0, s->center ? mom + size_t(c0) * 5 : nullptr, p->d.L, c,
+                                        stream),
                    "low modes");
     if (st != FKS_OK) return st;
   }
   return ok();
 }
 
-fks_status fks_sur_targets(fks_sur s, const float* q, const float* rho, float* t, int64_t n_cells, void* stream) {
+fks_status fks_sur_targets(fks_sur s, fks_plan p, const float* q, const float* rho, const double* mom, float* t,
+                           int64_t n_cells, void* stream) {
   fks_status st = sur_ready(s);
   if (st != FKS_OK) return st;
+  st = check_plan_ready(p);
+  if (st != FKS_OK) return st;
+  if (p->n != s->n) return fail(FKS_E_ARG, "plan and surrogate grids differ");
   if (n_cells < 0 || (n_cells > 0 && (!q || !rho || !t))) return fail(FKS_E_ARG, "bad buffers");
+  if (s->center && n_cells > 0 && !mom) return fail(FKS_E_ARG, "a centred surrogate needs the moments");
   if (n_cells == 0) return ok();
   if (n_cells > (int64_t(1) << 31) - 1) return fail(FKS_E_ARG, "too many cells");
-  return check_hip(fks::launch_sur_target(q, rho, 1.0f / s->scale, t, s->fout, n_cells, stream), "targets") == FKS_OK ? ok()
-                                                                                                  : FKS_E_DEVICE;
+  if (s->center)
+    st = check_hip(fks::launch_shift(s->n, q, s->fout, t, mom, +1, p->d.L, rho, s->scale, 2, nullptr, n_cells, stream),
+                   "centred targets");
+  else
+    st = check_hip(fks::launch_sur_target(q, rho, 1.0f / s->scale, t, s->fout, n_cells, stream), "targets");
+  return st == FKS_OK ? ok() : st;
 }
 
 fks_status fks_sur_forward(fks_sur s, const void* x, float* y, int64_t batch, void* stream) {
@@ -1044,12 +1087,18 @@ fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t
     float* qc = q + size_t(c0) * n3;
     float* rho = reinterpret_cast<float*>(B(s->d_ws, s->w_rho));
     double* r = d_indicator ? d_indicator + c0 : reinterpret_cast<double*>(B(s->d_ws, s->w_r));
-    st = fks_sur_features(s, p, fc, B(s->d_ws, s->w_x), rho, c, stream);
+    double* mom = s->center ? reinterpret_cast<double*>(B(s->d_ws, s->w_mom)) : nullptr;
+    st = fks_sur_features(s, p, fc, B(s->d_ws, s->w_x), rho, mom, c, stream);
     if (st == FKS_OK) st = sur_forward(s, B(s->d_ws, s->w_x), rows, stream);
-    if (st == FKS_OK)
-      st = check_hip(fks::launch_sur_output(reinterpret_cast<const float*>(B(s->d_ws, s->w_y)), n3, rho, s->scale, s->n,
-                                            p->d.L, qc, r, c, stream),
-                     "surrogate output");
+    if (st == FKS_OK) {
+      const float* y = reinterpret_cast<const float*>(B(s->d_ws, s->w_y));
+      if (s->center)  // back from the mean-velocity frame: q(v) = scale rho^2 y(v - u)
+        st = check_hip(fks::launch_shift(s->n, y, n3, qc, mom, -1, p->d.L, rho, s->scale, 1, r, c, stream),
+                       "surrogate output");
+      else
+        st = check_hip(fks::launch_sur_output(y, n3, rho, s->scale, s->n, p->d.L, qc, r, c, stream),
+                       "surrogate output");
+    }
     if (st != FKS_OK) return st;
     if (!(threshold >= 0.0)) continue;  // negative threshold: no fallback
     int* list = reinterpret_cast<int*>(B(s->d_ws, s->w_list));

@@ -69,14 +69,20 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
                        int ldb, const float* bias, float* Cf, void* Ch, const float* Zin, int ldc, void* stream);
 hipError_t launch_mse(const float* Y, const float* T, void* dY, int64_t n, double* partial, int blocks, void* stream);
 hipError_t launch_sum_partials(const double* partial, int n, double* out, void* stream);
-hipError_t launch_colsum(const void* X, int rows, int cols, float* out, void* stream);
+hipError_t launch_colsum(const void* X, int rows, int cols, float* out, float* partial, int max_blocks,
+                         void* stream);
+hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int M, int N, int K, int lda, int ldb,
+                                   const float* Zin, void* Ch, int splits, float* partial, void* stream);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, void* stream);
 hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int half, int npair, int K, int Kh, int mh,
-                           double box3, void* X, int ldx, float* rho, int64_t cells, void* stream);
+                           double box3, void* X, int ldx, float* rho, const double* mom, double L, int64_t cells,
+                           void* stream);
 hipError_t launch_sur_output(const float* Y, int ldy, const float* rho, float scale, int n, double L, float* q, double* r,
                              int64_t cells, void* stream);
 hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, float* t, int n3, int64_t cells, void* stream);
+hipError_t launch_shift(int n, const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
+                        const float* rho, float scale, int mode, double* r, int64_t cells, void* stream);
 hipError_t launch_compact(const double* r, int cells, double thr, int* list, int* count, void* stream);
 hipError_t launch_gather_cells(int scatter, const float* src, float* dst, const int* list, int count, int n3,
                                void* stream);

@@ -11,6 +11,7 @@
 // M, N, K must be multiples of 128, 128 and 32.
 #include <hip/hip_runtime.h>
 
+#include "fks_fft.hpp"
 #include "fks_internal.hpp"
 
 namespace fks {
@@ -31,14 +32,15 @@ enum GemmEpi {
   kEpiF32 = 0,        // Cf = acc (+ bias)
   kEpiBiasSilu = 1,   // Cf = z = acc + bias (pre-activation, kept for backward), Ch = bf16(silu(z))
   kEpiDSilu = 2,      // Ch = bf16(acc * silu'(Zin))
-  kEpiBiasBf16 = 3    // Ch = bf16(acc + bias)
+  kEpiBiasBf16 = 3,   // Ch = bf16(acc + bias)
+  kEpiPartial = 4     // split K: Cf[blockIdx.z][M][ldc] = partial acc
 };
 
 template <bool A_KM, bool B_KN, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, const __bf16* __restrict__ B, int M,
                                               int N, int K, int lda, int ldb, const float* __restrict__ bias,
                                               float* __restrict__ Cf, __bf16* __restrict__ Ch,
-                                              const float* __restrict__ Zin, int ldc) {
+                                              const float* __restrict__ Zin, int ldc, int k_split) {
   __shared__ __align__(16) __bf16 As[GBM * GLD];
   __shared__ __align__(16) __bf16 Bs[GBN * GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,7 +51,10 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
     for (int j = 0; j < 2; ++j)
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
-  for (int k0 = 0; k0 < K; k0 += GBK) {
+  // split K: blockIdx.z takes the k range [z k_split, (z + 1) k_split)
+  const int kb = blockIdx.z * k_split, ke = kb + k_split < K ? kb + k_split : K;
+  if constexpr (EPI == kEpiPartial) Cf += size_t(blockIdx.z) * M * ldc;
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
     // ---- stage A tile (GBM x GBK) as As[m][k]
     if constexpr (!A_KM) {
       const int r = tid >> 1, kh = (tid & 1) * 16;
@@ -110,13 +115,13 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn + j * 32 + (lane & 31);
-      const float bv = (bias && EPI != kEpiDSilu) ? bias[col] : 0.0f;
+      const float bv = (bias && EPI != kEpiDSilu && EPI != kEpiPartial) ? bias[col] : 0.0f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const size_t o = size_t(row) * ldc + col;
         const float v = acc[i][j][e];
-        if constexpr (EPI == kEpiF32) {
+        if constexpr (EPI == kEpiF32 || EPI == kEpiPartial) {
           Cf[o] = v + bv;
         } else if constexpr (EPI == kEpiBiasSilu) {
           const float z = v + bv;
@@ -131,17 +136,37 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
     }
 }
 
+// split-K reduction with the input-gradient epilogue: Ch = bf16(sum_z P[z] * silu'(Zin))
+__global__ __launch_bounds__(256) void k_splitk_dsilu(const float* __restrict__ Pz, int splits, int64_t mn,
+                                                      const float* __restrict__ Zin, __bf16* __restrict__ Ch) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < mn; i += int64_t(gridDim.x) * blockDim.x) {
+    float a = 0.0f;
+    for (int z = 0; z < splits; ++z) a += Pz[size_t(z) * mn + i];
+    Ch[i] = __bf16(a * dsilu_f(Zin[i]));
+  }
+}
+
 // ------------------------------------------------------------------------------------
-// MSE loss: dY = bf16(2 (Y - T) / count), per-block partial sums of (Y - T)^2 in FP64
+// MSE loss: dY = bf16(2 (Y - T) / count), per-block partial sums of (Y - T)^2 in FP64;
+// four elements per thread and step (n is a multiple of 4)
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
                                              __bf16* __restrict__ dY, int64_t n, double inv_count,
                                              double* __restrict__ partial) {
   __shared__ double red[4];
   double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    const float d = Y[i] - T[i];
-    s += double(d) * d;
-    dY[i] = __bf16(float(2.0 * inv_count) * d);
+  const float sc = float(2.0 * inv_count);
+  const int64_t n4 = n >> 2;
+  const float4* Y4 = reinterpret_cast<const float4*>(Y);
+  const float4* T4 = reinterpret_cast<const float4*>(T);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += int64_t(gridDim.x) * blockDim.x) {
+    const float4 y = Y4[i], t = T4[i];
+    const float d0 = y.x - t.x, d1 = y.y - t.y, d2 = y.z - t.z, d3 = y.w - t.w;
+    s += double(d0 * d0 + d1 * d1) + double(d2 * d2 + d3 * d3);
+    __bf16* o = dY + 4 * i;
+    o[0] = __bf16(sc * d0);
+    o[1] = __bf16(sc * d1);
+    o[2] = __bf16(sc * d2);
+    o[3] = __bf16(sc * d3);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -157,13 +182,23 @@ __global__ void k_sum_partials(const double* __restrict__ partial, int n, double
   }
 }
 
-// column sums of a [rows x cols] bf16 matrix (bias gradients), FP32 accumulation
-__global__ __launch_bounds__(256) void k_colsum(const __bf16* __restrict__ X, int rows, int cols,
-                                                float* __restrict__ out) {
+// column sums of a [rows x cols] bf16 matrix (bias gradients), FP32 accumulation, in two
+// passes: row block y of each column into partial[y][col], then the sum over blocks
+__global__ __launch_bounds__(256) void k_colsum_part(const __bf16* __restrict__ X, int rows, int cols, int rows_per,
+                                                     float* __restrict__ partial) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.y * rows_per, r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) s += float(X[size_t(r) * cols + c]);
+  partial[size_t(blockIdx.y) * cols + c] = s;
+}
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ partial, int blocks, int cols,
+                                                      float* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += float(X[size_t(r) * cols + c]);
+  for (int y = 0; y < blocks; ++y) s += partial[size_t(y) * cols + c];
   out[c] = s;
 }
 
@@ -190,8 +225,17 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
 template <typename T>
 __global__ __launch_bounds__(256) void k_lowmodes(const T* __restrict__ fhat_ri, int rows, int half, int npair, int K,
                                                   int Kh, int mh, double box3, __bf16* __restrict__ X, int ldx,
-                                                  float* __restrict__ rho) {
+                                                  float* __restrict__ rho, const double* __restrict__ mom, double L) {
   const int cell = blockIdx.x;
+  // centring: the coefficients of f(v + u), u the cell's mean velocity, are fhat_k e^{i xi_k.u}
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (mom) {
+    const double m0 = mom[size_t(cell) * 5];
+    ux = mom[size_t(cell) * 5 + 1] / m0;
+    uy = mom[size_t(cell) * 5 + 2] / m0;
+    uz = mom[size_t(cell) * 5 + 3] / m0;
+  }
+  const double wq = 3.14159265358979323846 / L;
   const T* fh = fhat_ri + size_t(cell) * rows * npair * 2;
   const int m = 2 * mh;
   // fhat(0): pencil (0, 0) is p = Kh*K, row n/2
@@ -208,7 +252,14 @@ __global__ __launch_bounds__(256) void k_lowmodes(const T* __restrict__ fhat_ri,
     // (-1)^(kx+ky+kz): the grid starts at v = -L, so the coefficient of exp(i xi.v) is the
     // index-space DFT times exp(i pi (kx+ky+kz))
     const double sg = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
-    const double re = sg * double(fh[e]) * inv, im = sg * double(fh[e + 1]) * inv * (direct ? 1.0 : -1.0);
+    double re = sg * double(fh[e]) * inv, im = sg * double(fh[e + 1]) * inv * (direct ? 1.0 : -1.0);
+    if (mom) {
+      double sn, cs;
+      sincos(wq * (kx * ux + ky * uy + kz * uz), &sn, &cs);
+      const double r2 = re * cs - im * sn, i2 = re * sn + im * cs;
+      re = r2;
+      im = i2;
+    }
     X[size_t(cell) * ldx + 2 * i] = __bf16(float(re));
     X[size_t(cell) * ldx + 2 * i + 1] = __bf16(float(im));
   }
@@ -256,6 +307,126 @@ __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y,
       r = fmax(r, fabs(sk) / (ak + 1e-300));
     }
     r_out[cell] = r;
+  }
+}
+
+// Spectral shift of whole cells: out(v) = m_c in(v + sign u_c) on the velocity grid, u_c the
+// cell's mean velocity (moments mom[c] = sum phi f dv^3), m_c = 1, scale rho_c^2 or
+// 1 / (scale rho_c^2) for mode 0, 1, 2.  The shift of the Fourier interpolant (Nyquist
+// modes dropped, as everywhere in the method) factorises over the axes, so it is three
+// passes of real 1-D line shifts (real DFT, phase e^{i pi k delta / L}, Hermitian inverse
+// DFT) on the cell held in LDS.  Optionally the moment-residual indicator of the output.
+template <int N>
+struct ShiftLds {
+  static constexpr int RS = N + 1;  // padded z row (floats)
+  static constexpr int KH1 = N / 2;
+  static constexpr size_t data_bytes = size_t(N) * N * RS * sizeof(float);
+  static constexpr size_t bytes = data_bytes + 3 * KH1 * sizeof(cpx<float>);
+  static_assert(bytes <= 156 * 1024, "cell does not fit in LDS");
+};
+
+__device__ __forceinline__ void block_sum10(double (&v)[10], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = 0; i < 10; ++i) {
+    double x = v[i];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[i * 16 + wid] = x;
+  }
+  __syncthreads();
+  for (int i = 0; i < 10; ++i) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[i * 16 + w];
+    v[i] = t;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int64_t ld_in, float* __restrict__ out,
+                                               const double* __restrict__ mom, int sign, double L,
+                                               const float* __restrict__ rho, float scale, int mode,
+                                               double* __restrict__ r_out) {
+  using SL = ShiftLds<N>;
+  constexpr int RS = SL::RS, KH1 = SL::KH1;
+  constexpr int N3 = N * N * N;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ double red[10 * 16];
+  float* sm = reinterpret_cast<float*>(lds_raw);
+  cpx<float>* ph = reinterpret_cast<cpx<float>*>(lds_raw + SL::data_bytes);
+  const int cell = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const double m0 = mom[size_t(cell) * 5];
+  const double u[3] = {mom[size_t(cell) * 5 + 1] / m0, mom[size_t(cell) * 5 + 2] / m0, mom[size_t(cell) * 5 + 3] / m0};
+  float mult = 1.0f;
+  if (mode == 1) mult = scale * rho[cell] * rho[cell];
+  if (mode == 2) mult = 1.0f / (scale * rho[cell] * rho[cell]);
+  // phase tables e^{i pi k sign u_a / L}, k = 0..N/2-1, with the 1/N of the inverse DFT
+  for (int i = tid; i < 3 * KH1; i += nt) {
+    const int a = i / KH1, k = i % KH1;
+    double sn, cs;
+    sincos(double(sign) * 3.14159265358979323846 * k * u[a] / L, &sn, &cs);
+    ph[i] = cpx<float>{float(cs / N), float(sn / N)};
+  }
+  const float* ic = in + size_t(cell) * ld_in;
+  for (int i = tid; i < N3; i += nt) sm[(i / N) * RS + (i % N)] = ic[i] * mult;
+  __syncthreads();
+  // axis 2 (z, stride 1), axis 1 (y, stride RS), axis 0 (x, stride N RS)
+  static_for<0, 3>([&](auto ax) {
+    constexpr int a = 2 - decltype(ax)::value;
+    for (int line = tid; line < N * N; line += nt) {
+      int base, stride;
+      if constexpr (a == 2) {
+        base = line * RS;
+        stride = 1;
+      } else if constexpr (a == 1) {
+        base = (line / N) * N * RS + (line % N);
+        stride = RS;
+      } else {
+        base = (line / N) * RS + (line % N);
+        stride = N * RS;
+      }
+      float r[N];
+      static_for<0, N>([&](auto j) { r[j] = sm[base + decltype(j)::value * stride]; });
+      cpx<float> o[KH1];
+      rdft_low<N, KH1>(r, o);
+      cpx<float> c[N];
+      static_for<0, KH1>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        const cpx<float> v = cmul(o[kk], ph[a * KH1 + kk]);
+        if constexpr (kk == 0) {
+          c[0] = cpx<float>{v.re, 0.0f};
+        } else {
+          c[kk] = v;
+          c[N - kk] = conj(v);
+        }
+      });
+      c[N / 2] = cpx<float>{0.0f, 0.0f};
+      dft<N, +1>(c);
+      static_for<0, N>([&](auto j) { sm[base + decltype(j)::value * stride] = c[j].re; });
+    }
+    __syncthreads();
+  });
+  float* oc = out + size_t(cell) * N3;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double dv = 2.0 * L / N;
+  for (int i = tid; i < N3; i += nt) {
+    const float qv = sm[(i / N) * RS + (i % N)];
+    oc[i] = qv;
+    if (r_out) {
+      const double vx = -L + (i / (N * N)) * dv, vy = -L + ((i / N) % N) * dv, vz = -L + (i % N) * dv;
+      const double ph5[5] = {1.0, vx, vy, vz, 0.5 * (vx * vx + vy * vy + vz * vz)};
+      const double d = double(qv);
+      for (int k = 0; k < 5; ++k) {
+        acc[k] += ph5[k] * d;
+        acc[5 + k] += fabs(ph5[k]) * fabs(d);
+      }
+    }
+  }
+  if (r_out) {
+    block_sum10(acc, red);
+    if (tid == 0) {
+      double rr = 0.0;
+      for (int k = 0; k < 5; ++k) rr = fmax(rr, fabs(acc[k]) / (acc[5 + k] + 1e-300));
+      r_out[cell] = rr;
+    }
   }
 }
 
@@ -321,7 +492,7 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
 #define GEMM_CASE(AK, BK, E)                                                                             \
   if (a_km == AK && b_kn == BK && epi == E) {                                                            \
     hipLaunchKernelGGL((k_gemm<AK, BK, E>), grid, dim3(256), 0, st, a, b, M, N, K, lda, ldb, bias, Cf, ch, \
-                       Zin, ldc);                                                                        \
+                       Zin, ldc, K);                                                                     \
     return hipGetLastError();                                                                            \
   }
   GEMM_CASE(false, false, kEpiF32)
@@ -332,6 +503,21 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
   GEMM_CASE(true, true, kEpiF32)
 #undef GEMM_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int M, int N, int K, int lda, int ldb,
+                                   const float* Zin, void* Ch, int splits, float* partial, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int k_split = K / splits;
+  hipLaunchKernelGGL((k_gemm<false, true, kEpiPartial>), dim3(N / GBN, M / GBM, splits), dim3(256), 0, st,
+                     static_cast<const __bf16*>(A), static_cast<const __bf16*>(B), M, N, K, lda, ldb,
+                     static_cast<const float*>(nullptr), partial, static_cast<__bf16*>(nullptr), Zin, N, k_split);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t mn = int64_t(M) * N;
+  hipLaunchKernelGGL(k_splitk_dsilu, dim3(unsigned((mn + 255) / 256 < 4096 ? (mn + 255) / 256 : 4096)), dim3(256), 0,
+                     st, partial, splits, mn, Zin, static_cast<__bf16*>(Ch));
+  return hipGetLastError();
 }
 
 hipError_t launch_mse(const float* Y, const float* T, void* dY, int64_t n, double* partial, int blocks,
@@ -346,9 +532,17 @@ hipError_t launch_sum_partials(const double* partial, int n, double* out, void* 
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const void* X, int rows, int cols, float* out, void* stream) {
-  hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     static_cast<const __bf16*>(X), rows, cols, out);
+hipError_t launch_colsum(const void* X, int rows, int cols, float* out, float* partial, int max_blocks,
+                         void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int blocks = (rows + 63) / 64;
+  if (blocks > max_blocks) blocks = max_blocks;
+  const int rows_per = (rows + blocks - 1) / blocks;
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 255) / 256, blocks), dim3(256), 0, st,
+                     static_cast<const __bf16*>(X), rows, cols, rows_per, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, partial, blocks, cols, out);
   return hipGetLastError();
 }
 
@@ -360,15 +554,16 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, 
 }
 
 hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int half, int npair, int K, int Kh, int mh,
-                           double box3, void* X, int ldx, float* rho, int64_t cells, void* stream) {
+                           double box3, void* X, int ldx, float* rho, const double* mom, double L, int64_t cells,
+                           void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype_is_f32)
     hipLaunchKernelGGL(k_lowmodes<float>, dim3(unsigned(cells)), dim3(256), 0, st, static_cast<const float*>(fhat),
-                       rows, half, npair, K, Kh, mh, box3, static_cast<__bf16*>(X), ldx, rho);
+                       rows, half, npair, K, Kh, mh, box3, static_cast<__bf16*>(X), ldx, rho, mom, L);
   else
     hipLaunchKernelGGL(k_lowmodes<double>, dim3(unsigned(cells)), dim3(256), 0, st,
                        static_cast<const double*>(fhat), rows, half, npair, K, Kh, mh, box3, static_cast<__bf16*>(X),
-                       ldx, rho);
+                       ldx, rho, mom, L);
   return hipGetLastError();
 }
 
@@ -391,6 +586,34 @@ hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, 
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int N>
+static hipError_t launch_shift_n(const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
+                                 const float* rho, float scale, int mode, double* r, int64_t cells, hipStream_t st) {
+  static bool attr_set = false;
+  constexpr size_t lds = ShiftLds<N>::bytes;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shift<N>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_shift<N>), dim3(unsigned(cells)), dim3(512), lds, st, in, ld_in, out, mom, sign, L, rho, scale,
+                     mode, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(int n, const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
+                        const float* rho, float scale, int mode, double* r, int64_t cells, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (n) {
+    case 8: return launch_shift_n<8>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
+    case 16: return launch_shift_n<16>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
+    case 24: return launch_shift_n<24>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
+    case 32: return launch_shift_n<32>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_compact(const double* r, int cells, double thr, int* list, int* count, void* stream) {

@@ -107,13 +107,14 @@ def test_surrogate_create_validation(lib):
     L = lib.lib()
     h = ctypes.c_void_p()
     # modes odd / too large, width not a multiple of 128, batch not a multiple of 128, bad scale
-    assert L.fks_sur_create(32, 7, 1024, 1024, 1.0, ctypes.byref(h)) == -1
-    assert L.fks_sur_create(32, 32, 1024, 1024, 1.0, ctypes.byref(h)) == -1
-    assert L.fks_sur_create(32, 8, 1000, 1024, 1.0, ctypes.byref(h)) == -1
-    assert L.fks_sur_create(32, 8, 1024, 1000, 1.0, ctypes.byref(h)) == -1
-    assert L.fks_sur_create(32, 8, 1024, 1024, 0.0, ctypes.byref(h)) == -1
-    assert L.fks_sur_create(12, 4, 128, 128, 1.0, ctypes.byref(h)) == -2   # 12^3 not a multiple of 128
-    assert L.fks_sur_create(32, 8, 1024, 1024, 1.0, ctypes.byref(h)) == 0
+    assert L.fks_sur_create(32, 7, 1024, 1024, 1.0, 0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 32, 1024, 1024, 1.0, 0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1000, 1024, 1.0, 0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1024, 1000, 1.0, 0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(32, 8, 1024, 1024, 0.0, 0, ctypes.byref(h)) == -1
+    assert L.fks_sur_create(12, 4, 128, 128, 1.0, 0, ctypes.byref(h)) == -2   # 12^3 not a multiple of 128
+    assert L.fks_sur_create(32, 8, 1024, 1024, 1.0, 4, ctypes.byref(h)) == -1        # unknown flag
+    assert L.fks_sur_create(32, 8, 1024, 1024, 1.0, 0, ctypes.byref(h)) == 0
     pb, wb, npar = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
     assert L.fks_sur_sizes(h, ctypes.byref(pb), ctypes.byref(wb), ctypes.byref(npar)) == 0
     n_in, w, n_out = 1024, 1024, 32 ** 3

@@ -97,21 +97,24 @@ def test_adam_step_matches_oracle():
             assert np.max(np.abs(a - b)) <= 1e-6 * max(1.0, np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("n,modes,dtype", [(8, 4, "f32"), (16, 8, "f64"), (32, 8, "f32")])
-def test_features_match_oracle(n, modes, dtype):
+@pytest.mark.parametrize("n,modes,dtype,center", [(8, 4, "f32", False), (16, 8, "f64", False), (32, 8, "f32", False),
+                                                   (16, 8, "f64", True), (32, 8, "f32", True)])
+def test_features_match_oracle(n, modes, dtype, center):
     import paper_1701_01608_amd as fks
     from fks_inputs import perturbed_maxwellians
     from oracle import mlp
     L = 8.0 if n >= 16 else 4.0
     f = perturbed_maxwellians(n, L, 5, seed=21)
     plan = fks.Plan(n=n, L=L, R=L * 4 / (3 + 2 ** 0.5), a1=2, a2=2, dtype=dtype, max_cells=4)
-    sur = fks.Surrogate(n=n, modes=modes, width=128, max_batch=128)
+    sur = fks.Surrogate(n=n, modes=modes, width=128, max_batch=128, center=center)
     fd = torch.as_tensor(f, dtype=plan.torch_dtype).cuda().contiguous()
-    x, rho = sur.features(plan, fd)
+    x, rho, mom = sur.features(plan, fd)
     x = x.float().cpu().numpy()
     rho = rho.cpu().numpy()
+    mom = mom.cpu().numpy()
     for c in range(5):
-        xr, rr = mlp.features(f[c], L, modes)
+        assert abs(mom[c, 0] - f[c].sum() * (2 * L / n) ** 3) <= 1e-6 * mom[c, 0]
+        xr, rr = mlp.features(f[c], L, modes, center=center)
         # BF16 storage: 2^-8 relative to the magnitude (|x| <= 1), plus FP32 transform error
         assert np.max(np.abs(x[c] - xr)) <= 2.0 ** -8 * np.max(np.abs(xr)) + 1e-6
         assert abs(rho[c] - rr) <= 1e-6 * rr
@@ -132,7 +135,7 @@ def test_infer_indicator_and_fallback():
     # no fallback: q = rho^2 y, indicator from the FP64 moments of q
     q_sur, nf = sur.infer(plan, fd, threshold=-1.0, indicator=r)
     assert nf == 0
-    x, rho = sur.features(plan, fd)
+    x, rho, _ = sur.features(plan, fd)
     xp = torch.zeros((256, sur.n_in), dtype=torch.bfloat16, device="cuda")
     xp[:cells] = x
     y = sur.forward(xp)[:cells]
@@ -157,6 +160,49 @@ def test_infer_indicator_and_fallback():
     assert torch.equal(q_all, q_spec)
 
 
+def test_centred_targets_and_inference_match_oracle():
+    """Centred surrogate: targets are Q(v + u) / (s rho^2) and predictions s rho^2 y(v - u),
+    both by the exact spectral shift; checked against the oracle's shift of the GPU's own
+    Q and network output, and the indicator against the oracle's on the result."""
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians
+    from oracle import mlp
+    n, L, cells, s = 16, 8.0, 130, 3e-3
+    f = perturbed_maxwellians(n, L, cells, seed=5)
+    plan = fks.Plan(n=n, L=L, R=6.0, a1=4, a2=4, dtype="f32", max_cells=64)
+    sur = fks.Surrogate(n=n, modes=8, width=128, max_batch=256, out_scale=s, center=True)
+    sur.set_params(mlp.init_params([sur.n_in, 128, 128, sur.n_out], 4))
+    fd = torch.as_tensor(f, dtype=torch.float32).cuda().contiguous()
+    x, rho, mom = sur.features(plan, fd)
+    q = plan.collide(fd).reshape(cells, -1)
+    t = sur.targets(plan, q, rho, mom).reshape(cells, n, n, n).double().cpu().numpy()
+    qn = q.reshape(cells, n, n, n).double().cpu().numpy()
+    rn = rho.double().cpu().numpy()
+    for c in range(0, cells, 29):
+        u = mlp.mean_velocity(f[c], L)
+        ref = mlp.spectral_shift(qn[c], u, L) / (s * rn[c] ** 2)
+        assert np.max(np.abs(t[c] - ref)) <= 1e-5 * np.max(np.abs(ref))
+    r = torch.empty(cells, dtype=torch.float64, device="cuda")
+    q_sur, nf = sur.infer(plan, fd, threshold=-1.0, indicator=r)
+    assert nf == 0
+    xp = torch.zeros((256, sur.n_in), dtype=torch.bfloat16, device="cuda")
+    xp[:cells] = x
+    y = sur.forward(xp)[:cells].reshape(cells, n, n, n).double().cpu().numpy()
+    qs = q_sur.double().cpu().numpy()
+    rr = r.cpu().numpy()
+    for c in range(0, cells, 29):
+        u = mlp.mean_velocity(f[c], L)
+        ref = mlp.spectral_shift(s * rn[c] ** 2 * y[c], -u, L)
+        assert np.max(np.abs(qs[c] - ref)) <= 1e-5 * np.max(np.abs(ref))
+        assert abs(rr[c] - mlp.moment_indicator(qs[c], L)) <= 1e-9 + 1e-6 * rr[c]
+    # fallback still selects exactly the cells above the threshold
+    thr = float(np.median(rr))
+    q_h, nf = sur.infer(plan, fd, threshold=thr)
+    a = torch.as_tensor(rr > thr, device="cuda")
+    assert nf == int(a.sum())
+    assert torch.equal(q_h[a], plan.collide(fd)[a])
+
+
 def test_training_learns_operator():
     """Train online (fresh perturbed Maxwellians every 8192 samples, labelled by the FP32
     spectral path, n = 16), then check the held-out error against the oracle's Q on
@@ -169,13 +215,13 @@ def test_training_learns_operator():
     n, L, R = 16, 8.0, 6.0
     plan = fks.Plan(n=n, L=L, R=R, a1=4, a2=4, dtype="f32", max_cells=4096)
     width, batch, chunk, steps = 512, 512, 8192, 3000
-    sur = fks.Surrogate(n=n, modes=8, width=width, max_batch=1024, out_scale=3e-3)
+    sur = fks.Surrogate(n=n, modes=8, width=width, max_batch=1024, out_scale=3e-3, center=True)
     sur.set_params(mlp.init_params([sur.n_in, width, width, sur.n_out], 1))
     losses, s, rnd = [], 0, 0
     while s < steps:
         f = perturbed_maxwellians_device(n, L, chunk, seed=1000 + rnd)
-        x, rho = sur.features(plan, f)
-        t = sur.targets(plan.collide(f).reshape(chunk, -1), rho)
+        x, rho, mom = sur.features(plan, f)
+        t = sur.targets(plan, plan.collide(f).reshape(chunk, -1), rho, mom)
         rnd += 1
         for j in range(0, chunk, batch):
             lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * s / steps))

@@ -71,3 +71,36 @@ def test_moment_indicator_special_cases():
     assert mlp.moment_indicator(qp, L) <= 1e-13
     # the indicator is scale invariant
     assert abs(mlp.moment_indicator(3.7 * q, L) - mlp.moment_indicator(q, L)) <= 1e-15
+
+
+def test_spectral_shift_moves_a_maxwellian():
+    # shifting the samples of M(u0) by delta gives the samples of M(u0 - delta) to
+    # spectral accuracy; the shift preserves mass exactly and shifting back restores the
+    # input.  Error budget at n = 32, L = 8, T = 1.1, centres within 0.5 of the origin:
+    # the dropped Nyquist coefficient is exp(-T (2 pi)^2 / 2) = 2e-10 of the mean and the
+    # periodic images at distance 15 contribute exp(-7.5^2 / 2.2) = 8e-12
+    import fks_inputs
+    n, L = 32, 8.0
+    u0, delta, T = np.array([0.3, -0.2, 0.1]), np.array([0.37, -0.21, 0.43]), 1.1
+    f = fks_inputs.maxwellian_on_grid(n, L, [1.2], [u0], [T])[0]
+    g = mlp.spectral_shift(f, delta, L)
+    expect = fks_inputs.maxwellian_on_grid(n, L, [1.2], [u0 - delta], [T])[0]
+    assert np.max(np.abs(g - expect)) <= 2e-9 * np.max(expect)
+    assert abs(g.sum() - f.sum()) <= 1e-13 * f.sum()
+    back = mlp.spectral_shift(g, -delta, L)           # = f with its Nyquist modes dropped
+    assert np.max(np.abs(back - mlp.spectral_shift(f, np.zeros(3), L))) <= 1e-14 * np.max(f)
+    # the mean velocity of the shifted samples moves by -delta
+    np.testing.assert_allclose(mlp.mean_velocity(g, L), u0 - delta, atol=1e-12)
+
+
+def test_centred_features_of_a_maxwellian_are_real():
+    # in its own mean-velocity frame a Maxwellian's coefficients are exp(-T |xi|^2 / 2)
+    import fks_inputs
+    n, L, m = 32, 8.0, 8
+    f = fks_inputs.maxwellian_on_grid(n, L, [0.9], [[0.7, -0.4, 1.3]], [0.8])[0]
+    x, _ = mlp.features(f, L, m, center=True)
+    k = np.arange(-m // 2, m // 2)
+    KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
+    xi2 = (np.pi / L) ** 2 * (KX ** 2 + KY ** 2 + KZ ** 2)
+    np.testing.assert_allclose(x[0::2], np.exp(-0.4 * xi2).ravel(), atol=1e-12)
+    np.testing.assert_allclose(x[1::2], 0.0, atol=1e-12)
