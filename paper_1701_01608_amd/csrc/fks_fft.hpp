@@ -125,6 +125,41 @@ __device__ __forceinline__ cpx<T> twiddle(cpx<T> x) {
 }
 
 constexpr int first_radix(int n) { return (n % 4 == 0) ? 4 : ((n % 3 == 0) ? 3 : 2); }
+constexpr int pow2_part(int n) { return (n % 2 == 0) ? 2 * pow2_part(n / 2) : 1; }
+// inverse of a modulo m (a, m coprime, small)
+constexpr int inv_mod(int a, int m) {
+  for (int t = 1; t < m; ++t)
+    if ((a * t) % m == 1) return t;
+  return 1;
+}
+
+template <int n, int sign, typename T>
+__device__ __forceinline__ void dft(cpx<T>* x);
+
+// Good-Thomas prime-factor DFT for n = N1 N2 with N1 = 2^a, N2 = 3^b coprime: input
+// index (N2 n1 + N1 n2) mod n and output index (N2 t1 k1 + N1 t2 k2) mod n (t1 = N2^-1
+// mod N1, t2 = N1^-1 mod N2) turn the length-n DFT into an N1 x N2 two-dimensional DFT
+// without inter-stage twiddle factors.
+template <int n, int sign, typename T>
+__device__ __forceinline__ void dft_pfa(cpx<T>* x) {
+  constexpr int N1 = pow2_part(n), N2 = n / N1;
+  constexpr int t1 = inv_mod(N2 % N1, N1), t2 = inv_mod(N1 % N2, N2);
+  cpx<T> a[N2][N1];
+  static_for<0, N2>([&](auto i2) {
+    static_for<0, N1>([&](auto i1) {
+      a[decltype(i2)::value][decltype(i1)::value] = x[(N2 * decltype(i1)::value + N1 * decltype(i2)::value) % n];
+    });
+    dft<N1, sign>(a[decltype(i2)::value]);
+  });
+  static_for<0, N1>([&](auto k1) {
+    cpx<T> b[N2];
+    static_for<0, N2>([&](auto i2) { b[decltype(i2)::value] = a[decltype(i2)::value][decltype(k1)::value]; });
+    dft<N2, sign>(b);
+    static_for<0, N2>([&](auto k2) {
+      x[(N2 * t1 * decltype(k1)::value + N1 * t2 * decltype(k2)::value) % n] = b[decltype(k2)::value];
+    });
+  });
+}
 
 template <int n, int sign, typename T>
 __device__ __forceinline__ void dft(cpx<T>* x) {
@@ -149,6 +184,8 @@ __device__ __forceinline__ void dft(cpx<T>* x) {
     x[1] = d02 + d13;
     x[2] = s02 - s13;
     x[3] = d02 - d13;
+  } else if constexpr (pow2_part(n) > 1 && pow2_part(n) < n) {
+    dft_pfa<n, sign>(x);
   } else {
     constexpr int r = first_radix(n);
     constexpr int m = n / r;
