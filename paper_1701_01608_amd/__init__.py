@@ -105,6 +105,15 @@ class Plan:
     def set_schedule(self, slabs, xcd_map=1):
         _lib.check(_lib.lib().fks_plan_set_schedule(self._h, int(slabs), int(xcd_map)))
 
+    def term_groups(self):
+        """(groups in effect, maximum for this plan)."""
+        tg, mx = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().fks_plan_get_term_groups(self._h, ctypes.byref(tg), ctypes.byref(mx)))
+        return tg.value, mx.value
+
+    def set_term_groups(self, tg):
+        _lib.check(_lib.lib().fks_plan_set_term_groups(self._h, int(tg)))
+
     def autotune(self, f, q=None, cache_path=None, stream=None):
         """Time the compiled slab schedules on f and keep the fastest (optional cache file)."""
         cells = self._check_f(f)

@@ -59,6 +59,8 @@ _SIGS = {
     "fks_plan_destroy": (None, [_VP]),
     "fks_plan_schedule": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "fks_plan_set_schedule": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "fks_plan_set_term_groups": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "fks_plan_get_term_groups": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "fks_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_char_p, _VP]),
     "fks_xport_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_VP)]),

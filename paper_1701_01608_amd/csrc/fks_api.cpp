@@ -158,6 +158,9 @@ struct fks_plan_s {
   // slab schedule (index into geo.variant_slabs) and workgroup-to-XCD mapping
   int variant = 0;
   int xcd_map = 1;
+  // term groups: each slab's term loop split over tg workgroups (latency of small
+  // batches); the workspace holds partials for up to tg_max groups
+  int tg = 1, tg_max = 1;
 };
 
 // Surrogate: FP32 master parameters, Adam moments, gradients and BF16 weight copies in
@@ -199,6 +202,8 @@ struct fks_xport_s {
 namespace {
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr int64_t kSmallBatch = 32;   // plans up to this many cells get term-group workspace
+constexpr int kMaxTermGroups = 8;
 
 // Separable terms in FP64: for every direction e_t (and radial node) the pair
 // (alpha_t(k), alpha'_t(k)) over the kept modes; the loss term (-1, lambda(k)) last.
@@ -359,6 +364,13 @@ fks_status check_plan_ready(const fks_plan_s* p) {
 }
 
 // Q / Euler over n_cells cells in chunks of max_cells.
+// groups actually used for tg requested: ceil(terms / ceil(terms / tg)), so none is empty
+int effective_groups(int n_terms, int tg) {
+  if (tg <= 1) return 1;
+  const int tpg = (n_terms + tg - 1) / tg;
+  return (n_terms + tpg - 1) / tpg;
+}
+
 fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, void* f_out, double dt,
                        int64_t n_cells, double* moments, void* stream) {
   const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
@@ -384,6 +396,7 @@ fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, 
     a.stream = stream;
     a.variant = p->variant;
     a.xcd_map = p->xcd_map;
+    a.term_groups = effective_groups(p->n_terms, p->tg);
     const fks_status s = check_hip(fks::launch_collide(f32, p->n, a), "collide launch");
     if (s != FKS_OK) return s;
   }
@@ -514,10 +527,11 @@ fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_
   off = round256(off + size_t(max_cells) * p->geo.fhat_elems * cs);
   p->off_scr = off;
   off = round256(off + size_t(max_cells) * p->geo.scratch_elems * cs);
+  p->tg_max = (max_cells <= kSmallBatch) ? (p->n_terms < kMaxTermGroups ? p->n_terms : kMaxTermGroups) : 1;
   p->off_g = off;
-  off = round256(off + size_t(max_cells) * p->geo.g_elems * p->esize);
+  off = round256(off + size_t(max_cells) * p->tg_max * p->geo.g_elems * p->esize);
   p->off_d = off;
-  off = round256(off + size_t(max_cells) * p->geo.d_elems * cs);
+  off = round256(off + size_t(max_cells) * p->tg_max * p->geo.d_elems * cs);
   p->ws_bytes = off;
   *out = p;
   return ok();
@@ -657,6 +671,22 @@ fks_status fks_plan_set_schedule(fks_plan p, int32_t slabs, int32_t xcd_map) {
   return fail(FKS_E_UNSUPPORTED, "no compiled schedule with %d slabs for n = %d", slabs, p->n);
 }
 
+fks_status fks_plan_set_term_groups(fks_plan p, int32_t tg) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (tg < 1) return fail(FKS_E_ARG, "term groups must be >= 1");
+  if (tg > p->tg_max)
+    return fail(FKS_E_UNSUPPORTED, "at most %d term groups for this plan (small-batch plans only)", p->tg_max);
+  p->tg = tg;
+  return ok();
+}
+
+fks_status fks_plan_get_term_groups(fks_plan p, int32_t* tg, int32_t* tg_max) {
+  if (!p || !tg || !tg_max) return fail(FKS_E_ARG, "null argument");
+  *tg = effective_groups(p->n_terms, p->tg);
+  *tg_max = p->tg_max;
+  return ok();
+}
+
 namespace {
 std::string device_name() {
   int dev = 0;
@@ -668,7 +698,7 @@ std::string device_name() {
 }
 
 // cache line: {"device":"gfx950","n":32,"dtype":"f32","terms":17,"cells":4096,"slabs":6,"xcd":1,"ms":15.0}
-bool cache_lookup(const char* path, const std::string& key, int* slabs, int* xcd) {
+bool cache_lookup(const char* path, const std::string& key, int* slabs, int* xcd, int* tg) {
   FILE* fp = std::fopen(path, "r");
   if (!fp) return false;
   char line[512];
@@ -680,6 +710,8 @@ bool cache_lookup(const char* path, const std::string& key, int* slabs, int* xcd
     if (ps == std::string::npos || px == std::string::npos) continue;
     *slabs = std::atoi(l.c_str() + ps + 8);
     *xcd = std::atoi(l.c_str() + px + 6);
+    const size_t pt = l.find("\"tg\":");
+    *tg = pt == std::string::npos ? 1 : std::atoi(l.c_str() + pt + 5);
     found = true;  // the last matching line wins
   }
   std::fclose(fp);
@@ -698,8 +730,9 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
                 device_name().c_str(), p->n, p->d.dtype == FKS_F32 ? "f32" : "f64", p->n_terms,
                 static_cast<long long>(n_cells));
   const std::string key(keybuf);
-  int cs = 0, cx = 0;
-  if (cache_path && cache_lookup(cache_path, key, &cs, &cx) && fks_plan_set_schedule(p, cs, cx) == FKS_OK)
+  int cs = 0, cx = 0, ct = 1;
+  if (cache_path && cache_lookup(cache_path, key, &cs, &cx, &ct) && fks_plan_set_schedule(p, cs, cx) == FKS_OK &&
+      fks_plan_set_term_groups(p, ct) == FKS_OK)
     return ok();
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -711,35 +744,41 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
     return s;
   }
   float best = 1e30f;
-  int best_v = p->variant, best_x = p->xcd_map;
+  int best_v = p->variant, best_x = p->xcd_map, best_t = p->tg;
   for (int v = 0; v < p->geo.n_variants && s == FKS_OK; ++v)
-    for (int x = 0; x < 2 && s == FKS_OK; ++x) {
-      p->variant = v;
-      p->xcd_map = x;
-      s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);  // warm-up
-      if (s != FKS_OK) break;
-      s = check_hip(hipEventRecord(e0, st), "event record");
-      for (int r = 0; r < 3 && s == FKS_OK; ++r) s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
-      if (s == FKS_OK) s = check_hip(hipEventRecord(e1, st), "event record");
-      if (s == FKS_OK) s = check_hip(hipEventSynchronize(e1), "event sync");
-      float ms = 0.f;
-      if (s == FKS_OK) s = check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-      if (s == FKS_OK && ms < best) {
-        best = ms;
-        best_v = v;
-        best_x = x;
+    for (int x = 0; x < 2 && s == FKS_OK; ++x)
+      for (int t = 1; t <= p->tg_max && s == FKS_OK; t *= 2) {
+        if (x && t > 1) continue;  // the XCD mapping applies to single-group schedules
+        p->variant = v;
+        p->xcd_map = x;
+        p->tg = t;
+        s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);  // warm-up
+        if (s != FKS_OK) break;
+        s = check_hip(hipEventRecord(e0, st), "event record");
+        for (int r = 0; r < 3 && s == FKS_OK; ++r)
+          s = run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
+        if (s == FKS_OK) s = check_hip(hipEventRecord(e1, st), "event record");
+        if (s == FKS_OK) s = check_hip(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        if (s == FKS_OK) s = check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (s == FKS_OK && ms < best) {
+          best = ms;
+          best_v = v;
+          best_x = x;
+          best_t = t;
+        }
       }
-    }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   p->variant = best_v;
   p->xcd_map = best_x;
+  p->tg = best_t;
   if (s != FKS_OK) return s;
   if (cache_path) {
     FILE* fp = std::fopen(cache_path, "a");
     if (fp) {
-      std::fprintf(fp, "{%s,\"slabs\":%d,\"xcd\":%d,\"ms\":%.4f}\n", key.c_str(), p->geo.variant_slabs[best_v], best_x,
-                   best / 3.0f);
+      std::fprintf(fp, "{%s,\"slabs\":%d,\"xcd\":%d,\"tg\":%d,\"ms\":%.4f}\n", key.c_str(),
+                   p->geo.variant_slabs[best_v], best_x, best_t, best / 3.0f);
       std::fclose(fp);
     }
   }

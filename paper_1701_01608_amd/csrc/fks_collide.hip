@@ -266,8 +266,8 @@ __global__ __launch_bounds__(512) void k_forward_lds(const T* __restrict__ f, cp
 // kernel 2: one slab of one cell, all separable terms
 template <typename T, int N, int S, int RID>
 __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T* __restrict__ tab,
-                                          int n_terms, T* __restrict__ Gw, cpx<T>* __restrict__ D,
-                                          cpx<T>* W) {
+                                          int n_terms, int t_begin, int t_end, T* __restrict__ Gw,
+                                          cpx<T>* __restrict__ D, cpx<T>* W) {
   using C = Cfg<T, N, S>;
   constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
   constexpr int NT = C::NT;
@@ -383,9 +383,9 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     // so the waves waiting on stage 1's loads overlap with the others' x-line transforms.
     cpx<T>* X = W + C::w_elems;
     using LdX = std::integral_constant<int, K>;
-    stage1(0, X, LdX{});
+    if (t_begin < t_end) stage1(t_begin, X, LdX{});
     __syncthreads();
-    for (int t = 0; t < n_terms; ++t) {
+    for (int t = t_begin; t < t_end; ++t) {
       // stage 2: y lines (z', kx): K modes -> P points; work item it = h*Z*K + line
       // computes the outputs y = 2j + h of one line
       {
@@ -404,7 +404,7 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
         }
       }
       __syncthreads();
-      if (t + 1 < n_terms) stage1(t + 1, X, LdX{});
+      if (t + 1 < t_end) stage1(t + 1, X, LdX{});
       // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
       {
         const int tid = opaque_tid();
@@ -423,7 +423,7 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     }
   } else {
     using LdW = std::integral_constant<int, WS>;
-    for (int t = 0; t < n_terms; ++t) {
+    for (int t = t_begin; t < t_end; ++t) {
       stage1(t, W, LdW{});
       __syncthreads();
       // stage 2: y lines (z', kx): K modes -> P points, in place
@@ -508,27 +508,32 @@ template <typename T, int N, int S>
 __global__ __launch_bounds__((Cfg<T, N, S>::NT)) void k_slab(const cpx<T>* __restrict__ fhat,
                                                            const T* __restrict__ tab, int n_terms,
                                                            T* __restrict__ G, cpx<T>* __restrict__ D,
-                                                           int xcd_map) {
+                                                           int xcd_map, int tg) {
   using C = Cfg<T, N, S>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cpx<T>* W = reinterpret_cast<cpx<T>*>(lds_raw);
-  // Workgroups are dealt round-robin to the 8 XCDs; with xcd_map the S slabs of one cell
-  // land on the same XCD (consecutive in its queue) so they share fhat through its L2.
+  // Work unit = (cell, term group g < tg); each unit has S slab workgroups and its own
+  // partial D (the finish kernel sums the groups).  Workgroups are dealt round-robin to
+  // the 8 XCDs; with xcd_map (tg = 1) the S slabs of one cell land on the same XCD
+  // (consecutive in its queue) so they share fhat through its L2.
   const int b = blockIdx.x;
-  int cell, r;
+  int unit, r;
   if (xcd_map) {
     const int j = b >> 3;
-    cell = (j / C::S) * 8 + (b & 7);
+    unit = (j / C::S) * 8 + (b & 7);
     r = j % C::S;
   } else {
-    cell = b / C::S;
+    unit = b / C::S;
     r = b % C::S;
   }
+  const int cell = unit / tg, g = unit - cell * tg;
+  const int tpg = (n_terms + tg - 1) / tg;
+  const int t0 = g * tpg, t1 = t0 + tpg < n_terms ? t0 + tpg : n_terms;
   const cpx<T>* fh = fhat + size_t(cell) * C::NRL * C::NPAIR;
-  T* Gs = C::GREG ? nullptr : G + (size_t(cell) * C::S + r) * (size_t(C::Z) * C::P * C::P);
-  cpx<T>* Ds = D + (size_t(cell) * C::S + r) * (size_t(C::KH1) * C::K * C::Z);
+  T* Gs = C::GREG ? nullptr : G + (size_t(unit) * C::S + r) * (size_t(C::Z) * C::P * C::P);
+  cpx<T>* Ds = D + (size_t(unit) * C::S + r) * (size_t(C::KH1) * C::K * C::Z);
   static_for<0, C::S>([&](auto rid) {
-    if (r == decltype(rid)::value) slab_body<T, N, S, decltype(rid)::value>(fh, tab, n_terms, Gs, Ds, W);
+    if (r == decltype(rid)::value) slab_body<T, N, S, decltype(rid)::value>(fh, tab, n_terms, t0, t1, Gs, Ds, W);
   });
 }
 
@@ -552,7 +557,7 @@ __device__ __forceinline__ void block_reduce5(double (&v)[5], double* red) {
 }
 
 template <typename T, int N, int S_>
-__global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cpx<T>* __restrict__ scratch,
+__global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, int tg, cpx<T>* __restrict__ scratch,
                                                 const T* f_in, T* q, T* f_out, double dt,
                                                 double* __restrict__ moments, EpiParams ep) {
   using C = Cfg<T, N, S_>;
@@ -560,7 +565,8 @@ __global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cp
   constexpr size_t N3 = size_t(N) * N * N;
   __shared__ double red[5 * 16];
   const int cell = blockIdx.x;
-  const cpx<T>* Dc = D + size_t(cell) * S * (size_t(KH1) * K * Z);
+  constexpr size_t DS = size_t(KH1) * K * Z;  // one slab partial
+  const cpx<T>* Dc = D + size_t(cell) * tg * S * DS;
   cpx<T>* sc = scratch + size_t(cell) * N3;
   T* Qtmp = reinterpret_cast<T*>(sc + size_t(KH1) * N * N);  // N^3 reals after the spectra
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(256) void k_finish(const cpx<T>* __restrict__ D, cp
       constexpr int b = ((kz % Z) + Z) % Z;
       cpx<T> acc = {T(0), T(0)};
       static_for<0, S>([&](auto r) {
-        const cpx<T> d = Dc[(size_t(decltype(r)::value) * KH1 * K + it) * Z + b];
+        const cpx<T> d = Dc[size_t(decltype(r)::value) * DS + size_t(it) * Z + b];
         acc = acc + twiddle<P, -1, long(kz) * decltype(r)::value>(d);
       });
       a[(kz + N) % N] = cpx<T>{T(acc.re * T(inv_p3)), T(acc.im * T(inv_p3))};
@@ -676,8 +682,8 @@ struct FinLds {
 };
 
 template <typename T, int N, int S_>
-__global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D, const T* f_in, T* q, T* f_out,
-                                                    double dt, double* __restrict__ moments, EpiParams ep) {
+__global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D, int tg, const T* f_in, T* q,
+                                                    T* f_out, double dt, double* __restrict__ moments, EpiParams ep) {
   using C = Cfg<T, N, S_>;
   using F = FinLds<T, N>;
   constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, Z = C::Z, S = C::S, RS = F::RS;
@@ -687,11 +693,13 @@ __global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cpx<T>* sm = reinterpret_cast<cpx<T>*>(lds_raw);
   const int cell = blockIdx.x;
-  const cpx<T>* Dc = D + size_t(cell) * S * (size_t(KH1) * K * Z);
+  constexpr size_t DS = size_t(KH1) * K * Z;  // one slab partial
+  const cpx<T>* Dc = D + size_t(cell) * tg * S * DS;
   const int tid = threadIdx.x, nt = blockDim.x;
   constexpr double inv_p3 = 1.0 / (double(P) * P * P);
 
-  // combine the S slab partials for every kept (kx >= 0, ky, kz), then z synthesis
+  // combine the S slab partials for every kept (kx >= 0, ky, kz), then z synthesis; with
+  // term groups the cell's partials sit in its first group slot (k_sum_groups)
   for (int it = tid; it < KH1 * K; it += nt) {
     const int kx = it / K, kyi = it % K;
     cpx<T> a[N];
@@ -701,7 +709,7 @@ __global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D
       constexpr int b = ((kz % Z) + Z) % Z;
       cpx<T> acc = {T(0), T(0)};
       static_for<0, S>([&](auto r) {
-        const cpx<T> d = Dc[(size_t(decltype(r)::value) * KH1 * K + it) * Z + b];
+        const cpx<T> d = Dc[size_t(decltype(r)::value) * DS + size_t(it) * Z + b];
         acc = acc + twiddle<P, -1, long(kz) * decltype(r)::value>(d);
       });
       a[(kz + N) % N] = cpx<T>{T(acc.re * T(inv_p3)), T(acc.im * T(inv_p3))};
@@ -840,6 +848,18 @@ hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, v
 }
 
 // ------------------------------------------------------------------------------------
+// term groups: add the partial spectra of groups 1..tg-1 of each cell into group 0
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_groups(cpx<T>* __restrict__ D, int tg, int unit_elems) {
+  cpx<T>* Dc = D + size_t(blockIdx.y) * tg * unit_elems;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < unit_elems; i += gridDim.x * blockDim.x) {
+    cpx<T> acc = Dc[i];
+    for (int g = 1; g < tg; ++g) acc = acc + Dc[size_t(g) * unit_elems + i];
+    Dc[i] = acc;
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // host launchers
 
 // forward transform of a batch: the LDS-resident kernel where one cell's partial
@@ -886,11 +906,17 @@ static hipError_t launch_collide_sched(const CollideArgs& a) {
   prof_mark(kProfForward, false, st);
   if (ef != hipSuccess) return ef;
   prof_mark(kProfSlab, true, st);
-  const int xcd = (a.xcd_map && cells % 8 == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_slab<T, N, S>), dim3(cells * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
-                     static_cast<const T*>(a.tables), a.n_terms, G, D, xcd);
+  const int tg = a.term_groups > 1 ? a.term_groups : 1;
+  const int xcd = (a.xcd_map && tg == 1 && cells % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_slab<T, N, S>), dim3(cells * tg * C::S), dim3(C::NT), C::lds_bytes, st, fhat,
+                     static_cast<const T*>(a.tables), a.n_terms, G, D, xcd, tg);
   prof_mark(kProfSlab, false, st);
   prof_mark(kProfFinish, true, st);
+  if (tg > 1) {
+    constexpr int ue = C::S * C::KH1 * C::K * C::Z;
+    hipLaunchKernelGGL((k_sum_groups<T>), dim3((ue + 255) / 256 < 64 ? (ue + 255) / 256 : 64, cells), dim3(256), 0,
+                       st, D, tg, ue);
+  }
   if constexpr (FinLds<T, N>::fits) {
     static bool fin_attr_set = false;
     if (!fin_attr_set) {
@@ -901,11 +927,11 @@ static hipError_t launch_collide_sched(const CollideArgs& a) {
       fin_attr_set = true;
     }
     constexpr size_t lds = FinLds<T, N>::bytes;
-    hipLaunchKernelGGL((k_finish_lds<T, N, S>), dim3(cells), dim3(512), lds, st, D,
+    hipLaunchKernelGGL((k_finish_lds<T, N, S>), dim3(cells), dim3(512), lds, st, D, tg,
                        static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
                        a.moments, a.ep);
   } else {
-    hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, scr,
+    hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, tg, scr,
                        static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
                        a.moments, a.ep);
   }

@@ -35,6 +35,7 @@ struct CollideArgs {
   void* stream;
   int variant;  // slab schedule index (SlabGeometry::variant_slabs)
   int xcd_map;  // 1: keep the S slabs of a cell on one XCD
+  int term_groups;  // split each slab's term loop over this many workgroups (partials summed)
 };
 
 struct SlabGeometry {

@@ -124,3 +124,24 @@ def test_surrogate_create_validation(lib):
     # calls before bind
     assert L.fks_sur_forward(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 128, None) == -5
     L.fks_sur_destroy(h)
+
+
+def test_term_groups_limits(lib):
+    L = lib.lib()
+    st, big = _create(lib, _desc(lib), max_cells=4096)
+    assert st == 0
+    assert L.fks_plan_set_term_groups(big, 1) == 0
+    assert L.fks_plan_set_term_groups(big, 2) == -2          # large-batch plan: no group workspace
+    L.fks_plan_destroy(big)
+    st, small = _create(lib, _desc(lib), max_cells=1)
+    assert st == 0
+    tg, mx = ctypes.c_int32(), ctypes.c_int32()
+    assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
+    assert (tg.value, mx.value) == (1, 8)
+    assert L.fks_plan_set_term_groups(small, 0) == -1
+    assert L.fks_plan_set_term_groups(small, 9) == -2
+    assert L.fks_plan_set_term_groups(small, 8) == 0
+    # 17 terms in groups of ceil(17/8) = 3: 6 groups are used, none empty
+    assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
+    assert tg.value == 6
+    L.fks_plan_destroy(small)

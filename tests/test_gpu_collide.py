@@ -246,3 +246,26 @@ def test_uneven_batch_as_one_graph():
         s.synchronize()
         for q, e in zip(qs, eager):
             assert torch.equal(q, e), f"replay {rep}"
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_term_groups_match_oracle(dtype):
+    # a small batch with each slab's term loop split over tg workgroups: same Q (up to the
+    # order of the FP additions), through collide and the relax/moment path
+    n, cells = 16, 3
+    plan = gpu_plan(n, dtype, max_cells=4)
+    f = fks_inputs.maxwellian_mixture(n, 8.0, cells, seed=808)
+    ft = torch.tensor(f, dtype=torch.float32 if dtype == "f32" else torch.float64, device="cuda")
+    ref, _ = oracle_q(ft.double().cpu().numpy(), n)
+    q1 = plan.collide(ft).double().cpu().numpy()
+    for tg in (2, 3, 8):
+        plan.set_term_groups(tg)
+        q = plan.collide(ft)
+        torch.cuda.synchronize()
+        used, mx = plan.term_groups()
+        err = rel(q.double().cpu().numpy(), ref)
+        print(f"{dtype} tg={tg} (used {used} of max {mx}) rel-L2 {err:.2e}", flush=True)
+        assert err <= TOL[dtype]
+        assert rel(q.double().cpu().numpy(), q1) <= TOL[dtype]
+    with pytest.raises(Exception):
+        plan.set_term_groups(mx + 1)
