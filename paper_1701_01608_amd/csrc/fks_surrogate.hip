@@ -41,8 +41,10 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
                                               int N, int K, int lda, int ldb, const float* __restrict__ bias,
                                               float* __restrict__ Cf, __bf16* __restrict__ Ch,
                                               const float* __restrict__ Zin, int ldc, int k_split) {
-  __shared__ __align__(16) __bf16 As[GBM * GLD];
-  __shared__ __align__(16) __bf16 Bs[GBN * GLD];
+  // two LDS stages: the global loads of k tile i+1 are in flight (in registers) while
+  // the matrix cores work on tile i
+  __shared__ __align__(16) __bf16 As[2][GBM * GLD];
+  __shared__ __align__(16) __bf16 Bs[2][GBN * GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -54,60 +56,82 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
   // split K: blockIdx.z takes the k range [z k_split, (z + 1) k_split)
   const int kb = blockIdx.z * k_split, ke = kb + k_split < K ? kb + k_split : K;
   if constexpr (EPI == kEpiPartial) Cf += size_t(blockIdx.z) * M * ldc;
-  for (int k0 = kb; k0 < ke; k0 += GBK) {
-    // ---- stage A tile (GBM x GBK) as As[m][k]
+
+  // per-thread share of one k tile: 2 x 16 bytes of A and of B (named registers: no
+  // address is taken, so nothing goes to private memory)
+  uint4 ra0, ra1, rb0, rb1;
+  auto load_tile = [&](int k0) {
     if constexpr (!A_KM) {
-      const int r = tid >> 1, kh = (tid & 1) * 16;
-      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(m0 + r) * lda + k0 + kh);
-      uint4* dst = reinterpret_cast<uint4*>(As + r * GLD + kh);
-      dst[0] = src[0];
-      dst[1] = src[1];
+      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(m0 + (tid >> 1)) * lda + k0 + (tid & 1) * 16);
+      ra0 = src[0];
+      ra1 = src[1];
     } else {
-      const int kr = tid >> 3, mc = (tid & 7) * 16;
-      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(k0 + kr) * lda + m0 + mc);
-      uint4 v0 = src[0], v1 = src[1];
-      const __bf16* h0 = reinterpret_cast<const __bf16*>(&v0);
-      const __bf16* h1 = reinterpret_cast<const __bf16*>(&v1);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        As[(mc + i) * GLD + kr] = h0[i];
-        As[(mc + 8 + i) * GLD + kr] = h1[i];
-      }
+      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(k0 + (tid >> 3)) * lda + m0 + (tid & 7) * 16);
+      ra0 = src[0];
+      ra1 = src[1];
     }
-    // ---- stage B tile (GBK x GBN) as Bs[n][k]
     if constexpr (!B_KN) {
-      const int r = tid >> 1, kh = (tid & 1) * 16;
-      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(n0 + r) * ldb + k0 + kh);
-      uint4* dst = reinterpret_cast<uint4*>(Bs + r * GLD + kh);
-      dst[0] = src[0];
-      dst[1] = src[1];
+      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(n0 + (tid >> 1)) * ldb + k0 + (tid & 1) * 16);
+      rb0 = src[0];
+      rb1 = src[1];
     } else {
-      const int kr = tid >> 3, nc = (tid & 7) * 16;
-      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(k0 + kr) * ldb + n0 + nc);
-      uint4 v0 = src[0], v1 = src[1];
-      const __bf16* h0 = reinterpret_cast<const __bf16*>(&v0);
-      const __bf16* h1 = reinterpret_cast<const __bf16*>(&v1);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        Bs[(nc + i) * GLD + kr] = h0[i];
-        Bs[(nc + 8 + i) * GLD + kr] = h1[i];
-      }
+      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(k0 + (tid >> 3)) * ldb + n0 + (tid & 7) * 16);
+      rb0 = src[0];
+      rb1 = src[1];
     }
-    __syncthreads();
+  };
+  // 16 consecutive bf16 of one k row scattered to 16 rows of a K-contiguous tile
+  auto scatter16 = [&](unsigned short* tile, int c0, int kr, const uint4& v0, const uint4& v1) {
+    const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      tile[(c0 + 2 * i) * GLD + kr] = static_cast<unsigned short>(w[i] & 0xffffu);
+      tile[(c0 + 2 * i + 1) * GLD + kr] = static_cast<unsigned short>(w[i] >> 16);
+    }
+  };
+  // LDS tiles K-contiguous: As[m][k], Bs[n][k]
+  auto store_tile = [&](int buf) {
+    if constexpr (!A_KM) {
+      uint4* dst = reinterpret_cast<uint4*>(As[buf] + (tid >> 1) * GLD + (tid & 1) * 16);
+      dst[0] = ra0;
+      dst[1] = ra1;
+    } else {
+      scatter16(reinterpret_cast<unsigned short*>(As[buf]), (tid & 7) * 16, tid >> 3, ra0, ra1);
+    }
+    if constexpr (!B_KN) {
+      uint4* dst = reinterpret_cast<uint4*>(Bs[buf] + (tid >> 1) * GLD + (tid & 1) * 16);
+      dst[0] = rb0;
+      dst[1] = rb1;
+    } else {
+      scatter16(reinterpret_cast<unsigned short*>(Bs[buf]), (tid & 7) * 16, tid >> 3, rb0, rb1);
+    }
+  };
+
+  if (kb < ke) {
+    load_tile(kb);
+    store_tile(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    const bool more = k0 + GBK < ke;
+    if (more) load_tile(k0 + GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const bf16x8*>(As + (wm + i * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5));
-        b[i] = *reinterpret_cast<const bf16x8*>(Bs + (wn + i * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5));
+        a[i] = *reinterpret_cast<const bf16x8*>(As[cur] + (wm + i * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5));
+        b[i] = *reinterpret_cast<const bf16x8*>(Bs[cur] + (wn + i * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5));
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) store_tile(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
   }
   // ---- epilogue: lane holds rows 8*(e/4) + 4*(lane/32) + e%4, column lane%32 of each tile
 #pragma unroll
