@@ -180,7 +180,8 @@ struct fks_sur_s {
   size_t p_master = 0, p_m = 0, p_v = 0, p_g = 0, p_w16 = 0;
   // workspace carve-up (bytes)
   size_t w_z1 = 0, w_z2 = 0, w_h1 = 0, w_h2 = 0, w_y = 0, w_dy = 0, w_dz1 = 0, w_dz2 = 0, w_part = 0, w_rho = 0,
-         w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0, w_cs = 0, w_sk = 0, w_mom = 0;
+         w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0, w_cs = 0, w_sk = 0, w_mom = 0, w_ta = 0,
+         w_tb = 0;
   int part_blocks = 1024;
   int splits = 1;  // split K of the output layer's input gradient (K = n^3)
   int64_t adam_t = 0;
@@ -827,6 +828,19 @@ fks_status sur_forward(fks_sur_s* s, const void* x, int64_t rows, void* stream) 
                    "surrogate layer 3");
 }
 
+// weight gradient G[M][N] = A^T B for A [r][M], B [r][N] (bf16, batch-major): both are
+// transposed to K-contiguous rows first so the GEMM stages its tiles with 16-byte moves
+fks_status weight_grad(fks_sur_s* s, const void* A, int M, const void* Bm, int N, int r, float* G, void* stream) {
+  void* at = B(s->d_ws, s->w_ta);
+  void* bt = B(s->d_ws, s->w_tb);
+  fks_status st = check_hip(fks::launch_transpose_bf16(A, r, M, at, stream), "transpose");
+  if (st == FKS_OK) st = check_hip(fks::launch_transpose_bf16(Bm, r, N, bt, stream), "transpose");
+  if (st == FKS_OK)
+    st = check_hip(fks::launch_gemm(0, 0, fks::kEpiF32_, at, bt, M, N, r, r, r, nullptr, G, nullptr, nullptr, N, stream),
+                   "weight gradient");
+  return st;
+}
+
 // gradients of the MSE of the batch against targets t into the gradient buffer
 fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t rows, double* d_loss, void* stream) {
   float* G = reinterpret_cast<float*>(B(s->d_params, s->p_g));
@@ -843,9 +857,7 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
     if (st != FKS_OK) return st;
   }
   // layer 3: dW3 = dY^T H2, db3 = colsum dY, dZ2 = (dY W3) silu'(Z2)
-  st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, dy, B(s->d_ws, s->w_h2), fo, w, r, fo, w, nullptr,
-                                  G + s->off_w[2], nullptr, nullptr, w, stream),
-                 "dW3");
+  st = weight_grad(s, dy, fo, B(s->d_ws, s->w_h2), w, r, G + s->off_w[2], stream);
   float* cs = reinterpret_cast<float*>(B(s->d_ws, s->w_cs));
   if (st == FKS_OK) st = check_hip(fks::launch_colsum(dy, r, fo, G + s->off_b[2], cs, kColsumBlocks, stream), "db3");
   // dZ2: K = n^3 is long and M x N = batch x width has few tiles: split K
@@ -856,10 +868,7 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
                                                  reinterpret_cast<float*>(B(s->d_ws, s->w_sk)), stream),
                    "dZ2");
   // layer 2
-  if (st == FKS_OK)
-    st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz2), B(s->d_ws, s->w_h1), w, w, r, w, w,
-                                    nullptr, G + s->off_w[1], nullptr, nullptr, w, stream),
-                   "dW2");
+  if (st == FKS_OK) st = weight_grad(s, B(s->d_ws, s->w_dz2), w, B(s->d_ws, s->w_h1), w, r, G + s->off_w[1], stream);
   if (st == FKS_OK)
     st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz2), r, w, G + s->off_b[1], cs, kColsumBlocks, stream), "db2");
   if (st == FKS_OK)
@@ -868,10 +877,7 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
                                     reinterpret_cast<const float*>(B(s->d_ws, s->w_z1)), w, stream),
                    "dZ1");
   // layer 1
-  if (st == FKS_OK)
-    st = check_hip(fks::launch_gemm(1, 1, fks::kEpiF32_, B(s->d_ws, s->w_dz1), x, w, fi, r, w, fi, nullptr,
-                                    G + s->off_w[0], nullptr, nullptr, fi, stream),
-                   "dW1");
+  if (st == FKS_OK) st = weight_grad(s, B(s->d_ws, s->w_dz1), w, x, fi, r, G + s->off_w[0], stream);
   if (st == FKS_OK)
     st = check_hip(fks::launch_colsum(B(s->d_ws, s->w_dz1), r, w, G + s->off_b[0], cs, kColsumBlocks, stream), "db1");
   return st;
@@ -939,6 +945,10 @@ fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_b
   s->w_gq = wb;   wb = round256(wb + 4 * Bm * fo);
   s->w_cs = wb;   wb = round256(wb + 4 * size_t(kColsumBlocks) * (fo > w ? fo : w));
   s->w_mom = wb;  wb = round256(wb + 8 * 5 * Bm);
+  // transposed operands of the weight gradients ([features][batch] bf16)
+  const size_t tmax = fo > w ? (fo > fi ? fo : fi) : (w > fi ? w : fi);
+  s->w_ta = wb;   wb = round256(wb + 2 * Bm * tmax);
+  s->w_tb = wb;   wb = round256(wb + 2 * Bm * (w > fi ? w : fi));
   // largest split count <= 16 whose K range is a whole number of 32-wide GEMM k steps
   s->splits = 1;
   for (int sp = 16; sp > 1; --sp)

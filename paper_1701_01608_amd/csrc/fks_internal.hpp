@@ -70,6 +70,7 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
                        int ldb, const float* bias, float* Cf, void* Ch, const float* Zin, int ldc, void* stream);
 hipError_t launch_mse(const float* Y, const float* T, void* dY, int64_t n, double* partial, int blocks, void* stream);
 hipError_t launch_sum_partials(const double* partial, int n, double* out, void* stream);
+hipError_t launch_transpose_bf16(const void* in, int rows, int cols, void* out, void* stream);
 hipError_t launch_colsum(const void* X, int rows, int cols, float* out, float* partial, int max_blocks,
                          void* stream);
 hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int M, int N, int K, int lda, int ldb,

@@ -198,12 +198,27 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const 
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * inv_count;
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += partial[i];
-    *out = s;
-  }
+// sum of n partials by one workgroup of 256 threads (tree over the waves)
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[c][r] = in[r][c] for a [rows][cols] bf16 matrix (64 x 64 tiles through LDS)
+__global__ __launch_bounds__(256) void k_transpose_bf16(const unsigned short* __restrict__ in, int rows, int cols,
+                                                        unsigned short* __restrict__ out) {
+  __shared__ unsigned short tile[64][65];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) tile[i][tx] = in[size_t(r0 + i) * cols + c0 + tx];
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) out[size_t(c0 + i) * rows + r0 + tx] = tile[tx][i];
 }
 
 // column sums of a [rows x cols] bf16 matrix (bias gradients), FP32 accumulation, in two
@@ -340,12 +355,15 @@ __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y,
 // modes dropped, as everywhere in the method) factorises over the axes, so it is three
 // passes of real 1-D line shifts (real DFT, phase e^{i pi k delta / L}, Hermitian inverse
 // DFT) on the cell held in LDS.  Optionally the moment-residual indicator of the output.
+constexpr int gcd_(int a, int b) { return b == 0 ? a : gcd_(b, a % b); }
+
 template <int N>
 struct ShiftLds {
   static constexpr int RS = N + 1;  // padded z row (floats)
   static constexpr int KH1 = N / 2;
   static constexpr size_t data_bytes = size_t(N) * N * RS * sizeof(float);
   static constexpr size_t bytes = data_bytes + 3 * KH1 * sizeof(cpx<float>);
+  static constexpr int TPB = (512 / (N * 64 / gcd_(N, 64))) * (N * 64 / gcd_(N, 64));  // threads per block
   static_assert(bytes <= 156 * 1024, "cell does not fit in LDS");
 };
 
@@ -411,40 +429,53 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
       static_for<0, N>([&](auto j) { r[j] = sm[base + decltype(j)::value * stride]; });
       cpx<float> o[KH1];
       rdft_low<N, KH1>(r, o);
-      cpx<float> c[N];
-      static_for<0, KH1>([&](auto k) {
+      static_for<0, KH1>([&](auto k) { o[k] = cmul(o[k], ph[a * KH1 + decltype(k)::value]); });
+      // real inverse from the Hermitian half (Nyquist zero) by one N/2-point complex DFT:
+      // z_j = x_{2j} + i x_{2j+1} = sum_k (X_k + conj X_{M-k} + i (X_k - conj X_{M-k}) w^k) e^{2 pi i jk/M}
+      constexpr int M = N / 2;
+      cpx<float> z[M];
+      static_for<0, M>([&](auto k) {
         constexpr int kk = decltype(k)::value;
-        const cpx<float> v = cmul(o[kk], ph[a * KH1 + kk]);
-        if constexpr (kk == 0) {
-          c[0] = cpx<float>{v.re, 0.0f};
-        } else {
-          c[kk] = v;
-          c[N - kk] = conj(v);
-        }
+        const cpx<float> xk = kk == 0 ? cpx<float>{o[0].re, 0.0f} : o[kk];
+        const cpx<float> xm = kk == 0 ? cpx<float>{0.0f, 0.0f} : conj(o[M - kk]);  // X_{M-k}, X_M = 0
+        const cpx<float> sp = xk + xm, dm = twiddle<N, +1, kk>(xk - xm);
+        z[kk] = cpx<float>{sp.re - dm.im, sp.im + dm.re};
       });
-      c[N / 2] = cpx<float>{0.0f, 0.0f};
-      dft<N, +1>(c);
-      static_for<0, N>([&](auto j) { sm[base + decltype(j)::value * stride] = c[j].re; });
+      dft<M, +1>(z);
+      static_for<0, M>([&](auto j) {
+        sm[base + 2 * decltype(j)::value * stride] = z[j].re;
+        sm[base + (2 * decltype(j)::value + 1) * stride] = z[j].im;
+      });
     }
     __syncthreads();
   });
   float* oc = out + size_t(cell) * N3;
-  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // moment sums in FP64; the block size is a multiple of N, so each thread's elements
+  // share one v_z and the sums separate: per element s0 += q, sx += vx q, sy += vy q,
+  // s2 += (vx^2 + vy^2) q (and the same with |.|), the v_z terms are added once
+  static_assert(ShiftLds<N>::TPB % N == 0 && ShiftLds<N>::TPB % 64 == 0, "block size must be a multiple of N and 64");
+  double s0 = 0, sx = 0, sy = 0, s2 = 0, a0 = 0, ax = 0, ay = 0, a2 = 0;
   const double dv = 2.0 * L / N;
   for (int i = tid; i < N3; i += nt) {
     const float qv = sm[(i / N) * RS + (i % N)];
     oc[i] = qv;
     if (r_out) {
-      const double vx = -L + (i / (N * N)) * dv, vy = -L + ((i / N) % N) * dv, vz = -L + (i % N) * dv;
-      const double ph5[5] = {1.0, vx, vy, vz, 0.5 * (vx * vx + vy * vy + vz * vz)};
-      const double d = double(qv);
-      for (int k = 0; k < 5; ++k) {
-        acc[k] += ph5[k] * d;
-        acc[5 + k] += fabs(ph5[k]) * fabs(d);
-      }
+      const double vx = -L + (i / (N * N)) * dv, vy = -L + ((i / N) % N) * dv;
+      const double d = double(qv), ad = fabs(d), r2 = vx * vx + vy * vy;
+      s0 += d;
+      sx += vx * d;
+      sy += vy * d;
+      s2 += r2 * d;
+      a0 += ad;
+      ax += fabs(vx) * ad;
+      ay += fabs(vy) * ad;
+      a2 += r2 * ad;
     }
   }
   if (r_out) {
+    const double vz = -L + (tid % N) * dv;
+    double acc[10] = {s0, sx, sy, vz * s0, 0.5 * (s2 + vz * vz * s0),
+                      a0, ax, ay, fabs(vz) * a0, 0.5 * (a2 + vz * vz * a0)};
     block_sum10(acc, red);
     if (tid == 0) {
       double rr = 0.0;
@@ -552,7 +583,14 @@ hipError_t launch_mse(const float* Y, const float* T, void* dY, int64_t n, doubl
 }
 
 hipError_t launch_sum_partials(const double* partial, int n, double* out, void* stream) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), partial, n, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), partial, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const void* in, int rows, int cols, void* out, void* stream) {
+  if (rows % 64 || cols % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose_bf16, dim3(cols / 64, rows / 64), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const unsigned short*>(in), rows, cols, static_cast<unsigned short*>(out));
   return hipGetLastError();
 }
 
@@ -623,8 +661,8 @@ static hipError_t launch_shift_n(const float* in, int64_t ld_in, float* out, con
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_shift<N>), dim3(unsigned(cells)), dim3(512), lds, st, in, ld_in, out, mom, sign, L, rho, scale,
-                     mode, r);
+  hipLaunchKernelGGL((k_shift<N>), dim3(unsigned(cells)), dim3(ShiftLds<N>::TPB), lds, st, in, ld_in, out, mom, sign,
+                     L, rho, scale, mode, r);
   return hipGetLastError();
 }
 
