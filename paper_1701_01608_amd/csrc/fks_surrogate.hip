@@ -382,6 +382,31 @@ __device__ __forceinline__ void block_sum10(double (&v)[10], double* red) {
   }
 }
 
+// one real line shift in registers: r (N samples) -> r (N samples of the shifted
+// interpolant), phase table ph (k = 0..N/2-1, 1/N of the inverse included)
+template <int N>
+__device__ __forceinline__ void shift_line(float* r, const cpx<float>* ph) {
+  constexpr int M = N / 2;
+  cpx<float> o[M];
+  rdft_low<N, M>(r, o);
+  static_for<0, M>([&](auto k) { o[k] = cmul(o[k], ph[decltype(k)::value]); });
+  // real inverse from the Hermitian half (Nyquist zero) by one N/2-point complex DFT:
+  // z_j = x_{2j} + i x_{2j+1} = sum_k (X_k + conj X_{M-k} + i (X_k - conj X_{M-k}) w^k) e^{2 pi i jk/M}
+  cpx<float> z[M];
+  static_for<0, M>([&](auto k) {
+    constexpr int kk = decltype(k)::value;
+    const cpx<float> xk = kk == 0 ? cpx<float>{o[0].re, 0.0f} : o[kk];
+    const cpx<float> xm = kk == 0 ? cpx<float>{0.0f, 0.0f} : conj(o[M - kk]);  // X_{M-k}, X_M = 0
+    const cpx<float> sp = xk + xm, dm = twiddle<N, +1, kk>(xk - xm);
+    z[kk] = cpx<float>{sp.re - dm.im, sp.im + dm.re};
+  });
+  dft<M, +1>(z);
+  static_for<0, M>([&](auto j) {
+    r[2 * decltype(j)::value] = z[j].re;
+    r[2 * decltype(j)::value + 1] = z[j].im;
+  });
+}
+
 template <int N>
 __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int64_t ld_in, float* __restrict__ out,
                                                const double* __restrict__ mom, int sign, double L,
@@ -389,7 +414,6 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
                                                double* __restrict__ r_out) {
   using SL = ShiftLds<N>;
   constexpr int RS = SL::RS, KH1 = SL::KH1;
-  constexpr int N3 = N * N * N;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double red[10 * 16];
   float* sm = reinterpret_cast<float*>(lds_raw);
@@ -407,69 +431,66 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
     sincos(double(sign) * 3.14159265358979323846 * k * u[a] / L, &sn, &cs);
     ph[i] = cpx<float>{float(cs / N), float(sn / N)};
   }
-  const float* ic = in + size_t(cell) * ld_in;
-  for (int i = tid; i < N3; i += nt) sm[(i / N) * RS + (i % N)] = ic[i] * mult;
   __syncthreads();
-  // axis 2 (z, stride 1), axis 1 (y, stride RS), axis 0 (x, stride N RS)
-  static_for<0, 3>([&](auto ax) {
-    constexpr int a = 2 - decltype(ax)::value;
-    for (int line = tid; line < N * N; line += nt) {
-      int base, stride;
-      if constexpr (a == 2) {
-        base = line * RS;
-        stride = 1;
-      } else if constexpr (a == 1) {
-        base = (line / N) * N * RS + (line % N);
-        stride = RS;
-      } else {
-        base = (line / N) * RS + (line % N);
-        stride = N * RS;
-      }
-      float r[N];
-      static_for<0, N>([&](auto j) { r[j] = sm[base + decltype(j)::value * stride]; });
-      cpx<float> o[KH1];
-      rdft_low<N, KH1>(r, o);
-      static_for<0, KH1>([&](auto k) { o[k] = cmul(o[k], ph[a * KH1 + decltype(k)::value]); });
-      // real inverse from the Hermitian half (Nyquist zero) by one N/2-point complex DFT:
-      // z_j = x_{2j} + i x_{2j+1} = sum_k (X_k + conj X_{M-k} + i (X_k - conj X_{M-k}) w^k) e^{2 pi i jk/M}
-      constexpr int M = N / 2;
-      cpx<float> z[M];
-      static_for<0, M>([&](auto k) {
-        constexpr int kk = decltype(k)::value;
-        const cpx<float> xk = kk == 0 ? cpx<float>{o[0].re, 0.0f} : o[kk];
-        const cpx<float> xm = kk == 0 ? cpx<float>{0.0f, 0.0f} : conj(o[M - kk]);  // X_{M-k}, X_M = 0
-        const cpx<float> sp = xk + xm, dm = twiddle<N, +1, kk>(xk - xm);
-        z[kk] = cpx<float>{sp.re - dm.im, sp.im + dm.re};
-      });
-      dft<M, +1>(z);
-      static_for<0, M>([&](auto j) {
-        sm[base + 2 * decltype(j)::value * stride] = z[j].re;
-        sm[base + (2 * decltype(j)::value + 1) * stride] = z[j].im;
-      });
-    }
-    __syncthreads();
-  });
-  float* oc = out + size_t(cell) * N3;
-  // moment sums in FP64; the block size is a multiple of N, so each thread's elements
-  // share one v_z and the sums separate: per element s0 += q, sx += vx q, sy += vy q,
-  // s2 += (vx^2 + vy^2) q (and the same with |.|), the v_z terms are added once
-  static_assert(ShiftLds<N>::TPB % N == 0 && ShiftLds<N>::TPB % 64 == 0, "block size must be a multiple of N and 64");
-  double s0 = 0, sx = 0, sy = 0, s2 = 0, a0 = 0, ax = 0, ay = 0, a2 = 0;
+  // z pass straight from global memory: row (x, y) is N contiguous floats
+  const float* ic = in + size_t(cell) * ld_in;
+  for (int line = tid; line < N * N; line += nt) {
+    float r[N];
+    const float4* src = reinterpret_cast<const float4*>(ic + size_t(line) * N);
+    static_for<0, N / 4>([&](auto q) {
+      const float4 v = src[decltype(q)::value];
+      r[4 * decltype(q)::value] = v.x * mult;
+      r[4 * decltype(q)::value + 1] = v.y * mult;
+      r[4 * decltype(q)::value + 2] = v.z * mult;
+      r[4 * decltype(q)::value + 3] = v.w * mult;
+    });
+    shift_line<N>(r, ph + 2 * KH1);
+    static_for<0, N>([&](auto j) { sm[line * RS + decltype(j)::value] = r[j]; });
+  }
+  __syncthreads();
+  // y pass in LDS: lines (x, z), stride RS
+  for (int line = tid; line < N * N; line += nt) {
+    const int base = (line / N) * N * RS + (line % N);
+    float r[N];
+    static_for<0, N>([&](auto j) { r[j] = sm[base + decltype(j)::value * RS]; });
+    shift_line<N>(r, ph + KH1);
+    static_for<0, N>([&](auto j) { sm[base + decltype(j)::value * RS] = r[j]; });
+  }
+  __syncthreads();
+  // x pass: lines (y, z), stride N RS in LDS; results go straight to global memory
+  // (lanes hold consecutive z: coalesced) with the FP64 moment sums of the output.
+  // The block size is a multiple of N, so a thread's lines share one z; per line the
+  // sums over x are taken first, then weighted by v_y (and v_z once at the end).
+  float* oc = out + size_t(cell) * N * N * N;
   const double dv = 2.0 * L / N;
-  for (int i = tid; i < N3; i += nt) {
-    const float qv = sm[(i / N) * RS + (i % N)];
-    oc[i] = qv;
+  double s0 = 0, sx = 0, sy = 0, s2 = 0, a0 = 0, ax = 0, ay = 0, a2 = 0;
+  for (int line = tid; line < N * N; line += nt) {
+    const int y = line / N, z = line % N;
+    const int base = y * RS + z;
+    float r[N];
+    static_for<0, N>([&](auto j) { r[j] = sm[base + decltype(j)::value * N * RS]; });
+    shift_line<N>(r, ph);
+    static_for<0, N>([&](auto j) { oc[(size_t(decltype(j)::value) * N + y) * N + z] = r[j]; });
     if (r_out) {
-      const double vx = -L + (i / (N * N)) * dv, vy = -L + ((i / N) % N) * dv;
-      const double d = double(qv), ad = fabs(d), r2 = vx * vx + vy * vy;
-      s0 += d;
-      sx += vx * d;
-      sy += vy * d;
-      s2 += r2 * d;
-      a0 += ad;
-      ax += fabs(vx) * ad;
-      ay += fabs(vy) * ad;
-      a2 += r2 * ad;
+      double l0 = 0, l1 = 0, l2 = 0, b0 = 0, b1 = 0, b2 = 0;
+      static_for<0, N>([&](auto j) {
+        const double vx = -L + decltype(j)::value * dv, d = double(r[j]), ad = fabs(d);
+        l0 += d;
+        l1 += vx * d;
+        l2 += vx * vx * d;
+        b0 += ad;
+        b1 += fabs(vx) * ad;
+        b2 += vx * vx * ad;
+      });
+      const double vy = -L + y * dv;
+      s0 += l0;
+      sx += l1;
+      sy += vy * l0;
+      s2 += l2 + vy * vy * l0;
+      a0 += b0;
+      ax += b1;
+      ay += fabs(vy) * b0;
+      a2 += b2 + vy * vy * b0;
     }
   }
   if (r_out) {
