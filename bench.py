@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "19057c3d816b0f47", "bytes": 2247749632}
+SLAB_TRAFFIC = {"sha": "4b45a8a8348add8f", "bytes": 2215124992}
 
 
 def kernel_sources_hash():

@@ -257,3 +257,15 @@ def test_training_learns_operator():
     corr = np.corrcoef(rank_r, rank_e)[0, 1]
     print("indicator/error rank correlation %.3f" % corr)
     assert corr > 0.3
+    # the hybrid: lowering the threshold moves cells to the spectral path; the fallback
+    # count never drops, the error against the spectral Q never rises, and threshold 0
+    # reproduces the spectral Q exactly
+    q2 = q_spec.double().pow(2).sum()
+    prev_nf, prev_err = -1, np.inf
+    for thr in (np.inf, float(np.quantile(rr, 0.75)), float(np.median(rr)), float(np.quantile(rr, 0.25)), 0.0):
+        q_h, nf = sur.infer(plan, f_val, threshold=thr)
+        e = float(((q_h - q_spec).double().pow(2).sum() / q2).sqrt())
+        print(f"threshold {thr:.3e}: fallback {nf}/{n_val}, rel-L2 {e:.3e}")
+        assert nf >= prev_nf and e <= prev_err * (1 + 1e-9) + 1e-12
+        prev_nf, prev_err = nf, e
+    assert nf == n_val and torch.equal(q_h, q_spec)
