@@ -14,6 +14,8 @@ Recipes (stated with the workloads they stand for):
     (the 3D Sod explosion initial state of the paper's Section 5, and a
     sinusoidal density perturbation of a unit Maxwellian).
   * bkw_initial: the Bobylev-Krook-Wu profile for Maxwell molecules.
+  * mlp_init: seeded initial weights of the surrogate network (random inputs of its
+    training, drawn here so that the device and the reference start alike).
 """
 
 import numpy as np
@@ -86,6 +88,21 @@ def perturbed_maxwellians_device(n, L, n_cells, seed=1, amp=0.3, device="cuda", 
         norm = torch.as_tensor(w[:, m] * rho[:, m] * (2.0 * np.pi * T[:, m]) ** -1.5, device=device)
         out += norm[:, None, None, None] * g[0][:, :, None, None] * g[1][:, None, :, None] * g[2][:, None, None, :]
     return out.to(dtype)
+
+
+def mlp_init(sizes, seed):
+    """Seeded initial parameters of a multilayer perceptron with layer sizes `sizes`:
+    W1, b1, W2, b2, ... with weights [out][in] drawn He-uniform U(-sqrt(6/fan_in),
+    sqrt(6/fan_in)) (the last layer scaled by 0.1) and zero biases, FP64."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for i in range(len(sizes) - 1):
+        bound = np.sqrt(6.0 / sizes[i])
+        W = rng.uniform(-bound, bound, (sizes[i + 1], sizes[i]))
+        if i == len(sizes) - 2:
+            W *= 0.1
+        params += [W, np.zeros(sizes[i + 1])]
+    return params
 
 
 def wave_box(n, L, shape, amp=0.1, rho0=1.0, T0=1.0):

@@ -31,17 +31,10 @@ def dsilu(z):
 
 
 def init_params(sizes, seed):
-    """He-uniform weights [out][in] and zero biases, drawn with numpy's seeded generator."""
-    rng = np.random.default_rng(seed)
-    params = []
-    for i in range(len(sizes) - 1):
-        fan_in = sizes[i]
-        bound = np.sqrt(6.0 / fan_in)
-        W = rng.uniform(-bound, bound, (sizes[i + 1], sizes[i]))
-        if i == len(sizes) - 2:
-            W *= 0.1      # small output layer
-        params += [W, np.zeros(sizes[i + 1])]
-    return params
+    """He-uniform weights [out][in] and zero biases: the seeded input generator shared
+    with the device runs (fks_inputs.mlp_init)."""
+    from fks_inputs import mlp_init
+    return mlp_init(sizes, seed)
 
 
 def forward(params, x):
