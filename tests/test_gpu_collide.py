@@ -269,3 +269,35 @@ def test_term_groups_match_oracle(dtype):
         assert rel(q.double().cpu().numpy(), q1) <= TOL[dtype]
     with pytest.raises(Exception):
         plan.set_term_groups(mx + 1)
+
+
+def test_uneven_batch_full_size_sampled():
+    # the uneven workload at full size in the benchmark's launch configuration: 1000
+    # instances each at n = 16, 24, 32 (M = 12), autotuned schedules, one graph launch;
+    # sampled instances of every group against the oracle, mass of every instance
+    from paper_1701_01608_amd import Graph, collide_grouped
+    plans, fs, qs, fnp = [], [], [], []
+    for i, n in enumerate((16, 24, 32)):
+        f = fks_inputs.maxwellian_mixture(n, 8.0, 1000, seed=1702 + i)
+        fnp.append(f)
+        fs.append(torch.tensor(f, dtype=torch.float32, device="cuda"))
+        qs.append(torch.empty_like(fs[-1]))
+        plans.append(gpu_plan(n, "f32", a1=3, a2=4, max_cells=1000))
+        plans[-1].autotune(fs[-1], qs[-1])
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with Graph(s) as g:
+            collide_grouped(plans, fs, qs, stream=s)
+        g.launch()
+    s.synchronize()
+    for n, f, q in zip((16, 24, 32), fs, qs):
+        qn = q.double().cpu().numpy()
+        assert np.isfinite(qn).all()
+        mass = np.abs(qn.sum(axis=(1, 2, 3))) / np.abs(qn).sum(axis=(1, 2, 3))
+        assert np.median(mass) <= 1e-6 and mass.max() <= 1e-4
+        idx = [0, 517, 999]
+        ref, _ = oracle_q(f[idx].double().cpu().numpy(), n, a1=3, a2=4)
+        err = rel(qn[idx], ref)
+        print(f"n={n} sampled rel-L2 {err:.2e}", flush=True)
+        assert err <= TOL["f32"]

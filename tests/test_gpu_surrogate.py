@@ -203,6 +203,39 @@ def test_centred_targets_and_inference_match_oracle():
     assert torch.equal(q_h[a], plan.collide(fd)[a])
 
 
+def test_full_size_inference_chunks():
+    """n = 32 in the benchmark's launch configuration (chunks of 4096 cells, centred):
+    threshold 0 sends every cell to the spectral path and must reproduce its Q exactly;
+    without fallback, sampled cells equal the oracle's shift of the network output."""
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians_device
+    from oracle import mlp
+    n, L, cells, s = 32, 8.0, 8192 + 130, 3e-3
+    plan = fks.Plan(n=n, L=L, R=6.0, a1=4, a2=4, dtype="f32", max_cells=4096)
+    sur = fks.Surrogate(n=n, modes=8, width=1024, max_batch=4096, out_scale=s, center=True)
+    sur.set_params(mlp.init_params([sur.n_in, 1024, 1024, sur.n_out], 2))
+    f = perturbed_maxwellians_device(n, L, cells, seed=3)
+    q_all, nf = sur.infer(plan, f, threshold=0.0)
+    assert nf == cells
+    q_spec = torch.empty_like(f)
+    for c0 in range(0, cells, 4096):
+        plan.collide(f[c0:c0 + 4096], q_spec[c0:c0 + 4096])
+    assert torch.equal(q_all, q_spec)
+    q_sur, nf = sur.infer(plan, f, threshold=-1.0)
+    assert nf == 0
+    idx = [0, 4095, 4096, cells - 1]
+    x, rho, _ = sur.features(plan, f[idx].contiguous())
+    xp = torch.zeros((128, sur.n_in), dtype=torch.bfloat16, device="cuda")
+    xp[:len(idx)] = x
+    y = sur.forward(xp)[:len(idx)].reshape(len(idx), n, n, n).double().cpu().numpy()
+    fn = f[idx].double().cpu().numpy()
+    rn = rho.double().cpu().numpy()
+    qs = q_sur[idx].double().cpu().numpy()
+    for j in range(len(idx)):
+        ref = mlp.spectral_shift(s * rn[j] ** 2 * y[j], -mlp.mean_velocity(fn[j], L), L)
+        assert np.max(np.abs(qs[j] - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
 def test_training_learns_operator():
     """Train online (fresh perturbed Maxwellians every 8192 samples, labelled by the FP32
     spectral path, n = 16), then check the held-out error against the oracle's Q on
