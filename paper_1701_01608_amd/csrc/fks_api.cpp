@@ -1024,9 +1024,19 @@ fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float
   if (p->n != s->n) return fail(FKS_E_ARG, "plan and surrogate grids differ");
   if (n_cells < 0 || (n_cells > 0 && (!f || !x || !rho))) return fail(FKS_E_ARG, "bad buffers");
   if (s->center && n_cells > 0 && !mom) return fail(FKS_E_ARG, "a centred surrogate needs the moments buffer");
+  if (n_cells == 0) return ok();
+  if (n_cells > (int64_t(1) << 31) - 1) return fail(FKS_E_ARG, "too many cells");
   const double dv = 2.0 * p->d.L / p->n;
   const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
   const int f32 = p->d.dtype == FKS_F32;
+  // pruned transform of the kept modes (one pass over f, moments included) where compiled
+  const hipError_t e = fks::launch_features(f32, p->n, s->modes, f, x, s->fin, rho, mom, s->center ? 1 : 0, p->d.L,
+                                            n_cells, stream);
+  if (e != hipErrorNotSupported) {
+    st = check_hip(e, "features");
+    return st == FKS_OK ? ok() : st;
+  }
+  // other grids: full transform, then the low modes
   const double box3 = 8.0 * p->d.L * p->d.L * p->d.L;
   unsigned char* ws = static_cast<unsigned char*>(p->d_ws);
   for (int64_t c0 = 0; c0 < n_cells; c0 += p->max_cells) {

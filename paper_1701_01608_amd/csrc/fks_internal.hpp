@@ -85,6 +85,8 @@ hipError_t launch_sur_output(const float* Y, int ldy, const float* rho, float sc
 hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, float* t, int n3, int64_t cells, void* stream);
 hipError_t launch_shift(int n, const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
                         const float* rho, float scale, int mode, double* r, int64_t cells, void* stream);
+hipError_t launch_features(int dtype_is_f32, int n, int modes, const void* f, void* X, int ldx, float* rho,
+                           double* mom, int center, double L, int64_t cells, void* stream);
 hipError_t launch_compact(const double* r, int cells, double thr, int* list, int* count, void* stream);
 hipError_t launch_gather_cells(int scatter, const float* src, float* dst, const int* list, int count, int n3,
                                void* stream);

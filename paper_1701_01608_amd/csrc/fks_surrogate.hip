@@ -304,6 +304,156 @@ __global__ __launch_bounds__(256) void k_lowmodes(const T* __restrict__ fhat_ri,
   }
 }
 
+__device__ __forceinline__ void block_reduce_moments(double (&v)[5], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < 5; ++i) {
+    double x = v[i];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[i * 16 + wid] = x;
+  }
+  __syncthreads();
+  for (int i = 0; i < 5; ++i) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[i * 16 + w];
+    v[i] = t;
+  }
+}
+
+// Pruned feature transform: only the lowest modes k in [-MH, MH-1]^3 of f, by direct
+// separable sums with compile-time twiddles (z: the N real samples of a row against
+// k_z = 0..MH, the negative k_z by conjugation; then y and x over the complex partials),
+// reading f once.  The same pass forms the FP64 moments sum phi f dv^3 of the cell, from
+// which rho and (centring) the mean velocity u follow.  Output as k_lowmodes.
+template <typename T, int N, int MH>
+__global__ __launch_bounds__(256) void k_features(const T* __restrict__ f, __bf16* __restrict__ X, int ldx,
+                                                  float* __restrict__ rho_out, double* __restrict__ mom_out,
+                                                  int center, double L) {
+  constexpr int M = 2 * MH;
+  static_assert(MH <= N / 2 - 1, "modes beyond the kept set");
+  __shared__ cpx<float> zs[N * N][M];     // z partials [x][y][kz + MH]
+  __shared__ cpx<float> ys[N][M][M];      // y partials [x][ky + MH][kz + MH]
+  __shared__ double red[5 * 16];
+  const int cell = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const T* fc = f + size_t(cell) * N * N * N;
+  const double dv = 2.0 * L / N;
+  // index moments (FP64, literal integer weights): sum f, sum i f, sum j f, sum k f,
+  // sum (i^2 + j^2 + k^2) f over grid indices; the velocity moments follow after the
+  // block sum from v = -L + index dv
+  double m[5] = {0, 0, 0, 0, 0};
+  // z pass + moments
+  for (int row = tid; row < N * N; row += nt) {
+    T r[N];
+    static_for<0, N>([&](auto z) { r[z] = fc[size_t(row) * N + decltype(z)::value]; });
+    double s0 = 0, sz = 0, szz = 0;
+    static_for<0, N>([&](auto z) {
+      constexpr double iz = double(decltype(z)::value);
+      const double d = double(r[z]);
+      s0 += d;
+      sz += iz * d;
+      szz += (iz * iz) * d;
+      if constexpr (decltype(z)::value % 8 == 7) sched_fence();
+    });
+    const double ix = double(row / N), iy = double(row % N);
+    m[0] += s0;
+    m[1] += ix * s0;
+    m[2] += iy * s0;
+    m[3] += sz;
+    m[4] += (ix * ix + iy * iy) * s0 + szz;
+    static_for<0, MH + 1>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      float re = 0.0f, im = 0.0f;
+      static_for<0, N>([&](auto z) {
+        constexpr sc w = sincos2pi(-long(k) * decltype(z)::value, N);  // e^{-2 pi i k z / N}
+        if constexpr (w.c != 0.0) re += float(w.c) * float(r[z]);
+        if constexpr (w.s != 0.0) im += float(w.s) * float(r[z]);
+      });
+      if constexpr (k < MH) zs[row][MH + k] = cpx<float>{re, im};
+      if constexpr (k > 0) zs[row][MH - k] = cpx<float>{re, -im};
+      sched_fence();
+    });
+  }
+  // y pass: lines (x, kz)
+  __syncthreads();
+  for (int it = tid; it < N * M; it += nt) {
+    const int x = it / M, kzi = it % M;
+    cpx<float> acc[M];
+    static_for<0, M>([&](auto k) { acc[k] = cpx<float>{0.0f, 0.0f}; });
+    static_for<0, N>([&](auto yy) {
+      constexpr int y = decltype(yy)::value;
+      const cpx<float> v = zs[x * N + y][kzi];
+      static_for<0, M>([&](auto kk) {
+        constexpr sc w = sincos2pi(-long(decltype(kk)::value - MH) * y, N);
+        acc[kk] = acc[kk] + cmul(v, cpx<float>{float(w.c), float(w.s)});
+      });
+      if constexpr (y % 8 == 7) sched_fence();
+    });
+    static_for<0, M>([&](auto k) { ys[x][decltype(k)::value][kzi] = acc[k]; });
+  }
+  block_reduce_moments(m, red);
+  __syncthreads();
+  {
+    const double a0 = m[0], ax = m[1], ay = m[2], az = m[3], b = m[4];
+    m[1] = -L * a0 + dv * ax;
+    m[2] = -L * a0 + dv * ay;
+    m[3] = -L * a0 + dv * az;
+    m[4] = 0.5 * (3.0 * L * L * a0 - 2.0 * L * dv * (ax + ay + az) + dv * dv * b);
+  }
+  const double S = m[0];  // sum of f over the grid
+  const double inv = S != 0.0 ? 1.0 / S : 0.0;
+  double ux = 0, uy = 0, uz = 0;
+  if (S != 0.0) {
+    ux = m[1] / S;
+    uy = m[2] / S;
+    uz = m[3] / S;
+  }
+  if (tid == 0) {
+    const double w3 = dv * dv * dv;
+    rho_out[cell] = float(S * w3);
+    if (mom_out)
+      for (int i = 0; i < 5; ++i) mom_out[size_t(cell) * 5 + i] = m[i] * w3;
+  }
+  // x pass: lines (ky, kz) -> kx; normalise, grid-origin and centring phases, bf16
+  const double wq = 3.14159265358979323846 / L;
+  for (int it = tid; it < M * M; it += nt) {
+    const int kyi = it / M, kzi = it % M;
+    const int ky = kyi - MH, kz = kzi - MH;
+    cpx<float> acc[M];
+    static_for<0, M>([&](auto k) { acc[k] = cpx<float>{0.0f, 0.0f}; });
+    static_for<0, N>([&](auto xx) {
+      constexpr int x = decltype(xx)::value;
+      const cpx<float> v = ys[x][kyi][kzi];
+      static_for<0, M>([&](auto kk) {
+        constexpr sc w = sincos2pi(-long(decltype(kk)::value - MH) * x, N);
+        acc[kk] = acc[kk] + cmul(v, cpx<float>{float(w.c), float(w.s)});
+      });
+      if constexpr (x % 8 == 7) sched_fence();
+    });
+    // centring phase exp(i wq k.u), advanced along kx by repeated FP64 rotation
+    double pc = 1.0, ps = 0.0, sc_ = 1.0, ss_ = 0.0;
+    if (center) {
+      sincos(wq * (-MH * ux + ky * uy + kz * uz), &ps, &pc);
+      sincos(wq * ux, &ss_, &sc_);
+    }
+    static_for<0, M>([&](auto kk) {
+      constexpr int kx = decltype(kk)::value - MH;
+      double re = double(acc[kk].re) * inv, im = double(acc[kk].im) * inv;
+      if ((kx + ky + kz) & 1) {
+        re = -re;
+        im = -im;
+      }
+      const double r2 = re * pc - im * ps, i2 = re * ps + im * pc;
+      re = r2;
+      im = i2;
+      const double pc2 = pc * sc_ - ps * ss_, ps2 = pc * ss_ + ps * sc_;
+      pc = pc2;
+      ps = ps2;
+      const int i = (decltype(kk)::value * M + kyi) * M + kzi;
+      X[size_t(cell) * ldx + 2 * i] = __bf16(float(re));
+      X[size_t(cell) * ldx + 2 * i + 1] = __bf16(float(im));
+    });
+  }
+}
+
 // Surrogate output to Q: q = scale * rho^2 * y; moment-residual indicator
 // r = max_i |sum_k phi_i(v_k) q_k| / (sum_k |phi_i(v_k)| |q_k|), phi = (1, v, |v|^2/2), FP64.
 __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y, int ldy, const float* __restrict__ rho,
@@ -634,6 +784,30 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, 
   hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), p, m, v,
                      g, static_cast<__bf16*>(p16), n, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
+}
+
+template <typename T, int N, int MH>
+static hipError_t launch_features_n(const void* f, void* X, int ldx, float* rho, double* mom, int center, double L,
+                                    int64_t cells, hipStream_t st) {
+  hipLaunchKernelGGL((k_features<T, N, MH>), dim3(unsigned(cells)), dim3(256), 0, st, static_cast<const T*>(f),
+                     static_cast<__bf16*>(X), ldx, rho, mom, center, L);
+  return hipGetLastError();
+}
+
+// pruned feature transform for the compiled (n, modes) pairs; hipErrorNotSupported
+// otherwise (the caller then takes the full transform)
+hipError_t launch_features(int dtype_is_f32, int n, int modes, const void* f, void* X, int ldx, float* rho,
+                           double* mom, int center, double L, int64_t cells, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+#define FEAT(T, NN, MM) \
+  if (n == NN && modes == 2 * MM) return launch_features_n<T, NN, MM>(f, X, ldx, rho, mom, center, L, cells, st);
+  if (dtype_is_f32) {
+    FEAT(float, 8, 2) FEAT(float, 16, 2) FEAT(float, 16, 4) FEAT(float, 24, 4) FEAT(float, 32, 4)
+  } else {
+    FEAT(double, 8, 2) FEAT(double, 16, 2) FEAT(double, 16, 4) FEAT(double, 24, 4) FEAT(double, 32, 4)
+  }
+#undef FEAT
+  return hipErrorNotSupported;
 }
 
 hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int half, int npair, int K, int Kh, int mh,

@@ -97,8 +97,11 @@ def test_adam_step_matches_oracle():
             assert np.max(np.abs(a - b)) <= 1e-6 * max(1.0, np.max(np.abs(b)))
 
 
+# (16, 12) has no pruned kernel and takes the full transform followed by the low modes
 @pytest.mark.parametrize("n,modes,dtype,center", [(8, 4, "f32", False), (16, 8, "f64", False), (32, 8, "f32", False),
-                                                   (16, 8, "f64", True), (32, 8, "f32", True)])
+                                                   (16, 8, "f64", True), (32, 8, "f32", True), (24, 8, "f64", True),
+                                                   (16, 4, "f32", True), (16, 12, "f32", True),
+                                                   (16, 12, "f64", False)])
 def test_features_match_oracle(n, modes, dtype, center):
     import paper_1701_01608_amd as fks
     from fks_inputs import perturbed_maxwellians
