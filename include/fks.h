@@ -230,7 +230,9 @@ fks_status fks_sur_get(fks_sur s, int32_t which, float* host, void* stream);
 /* Features of n_cells distributions f (plan dtype, plan grid n == surrogate n):
  * x [n_cells][2 m^3] BF16 (device), rho [n_cells] FP32 (device), and, if mom != NULL,
  * the FP64 moments sum phi f dv^3, phi = (1, v, |v|^2/2), [n_cells][5] (device; required
- * for a centred surrogate).  Uses the plan's workspace. */
+ * for a centred surrogate).  The kept modes come from a pruned transform that reads f once
+ * (n = 8, 16, 24, 32 with the mode counts the surrogate accepts there: 4; 4, 8; 8; 8);
+ * other (n, m) pairs take the plan's full forward transform through its workspace. */
 fks_status fks_sur_features(fks_sur s, fks_plan plan, const void* f, void* x, float* rho, double* mom,
                             int64_t n_cells, void* stream);
 /* Training targets t = q / (s rho^2) ([n_cells][n^3] FP32, device; t may equal q); for a

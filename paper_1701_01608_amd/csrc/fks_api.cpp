@@ -181,7 +181,7 @@ struct fks_sur_s {
   // workspace carve-up (bytes)
   size_t w_z1 = 0, w_z2 = 0, w_h1 = 0, w_h2 = 0, w_y = 0, w_dy = 0, w_dz1 = 0, w_dz2 = 0, w_part = 0, w_rho = 0,
          w_r = 0, w_list = 0, w_cnt = 0, w_x = 0, w_gf = 0, w_gq = 0, w_cs = 0, w_sk = 0, w_mom = 0, w_ta = 0,
-         w_tb = 0;
+         w_tb = 0, w_w3t = 0;
   int part_blocks = 1024;
   int splits = 1;  // split K of the output layer's input gradient (K = n^3)
   int64_t adam_t = 0;
@@ -808,7 +808,8 @@ fks_status sur_ready(const fks_sur_s* s) {
 }
 
 // forward pass of a batch (rows multiple of 128) into Z1, H1, Z2, H2 and Y
-fks_status sur_forward(fks_sur_s* s, const void* x, int64_t rows, void* stream) {
+// forward pass; the output layer writes y_out ([rows][n^3] FP32) or, if null, the workspace
+fks_status sur_forward(fks_sur_s* s, const void* x, int64_t rows, void* stream, float* y_out = nullptr) {
   const float* P = reinterpret_cast<const float*>(B(s->d_params, s->p_master));
   const unsigned char* W16 = B(s->d_params, s->p_w16);
   const int w = s->width, fi = s->fin, fo = s->fout, r = int(rows);
@@ -823,8 +824,8 @@ fks_status sur_forward(fks_sur_s* s, const void* x, int64_t rows, void* stream) 
                  "surrogate layer 2");
   if (st != FKS_OK) return st;
   return check_hip(fks::launch_gemm(0, 0, fks::kEpiF32_, B(s->d_ws, s->w_h2), W16 + 2 * s->off_w[2], r, fo, w, w, w,
-                                    P + s->off_b[2], reinterpret_cast<float*>(B(s->d_ws, s->w_y)), nullptr, nullptr,
-                                    fo, stream),
+                                    P + s->off_b[2], y_out ? y_out : reinterpret_cast<float*>(B(s->d_ws, s->w_y)),
+                                    nullptr, nullptr, fo, stream),
                    "surrogate layer 3");
 }
 
@@ -860,13 +861,25 @@ fks_status sur_backward(fks_sur_s* s, const void* x, const float* t, int64_t row
   st = weight_grad(s, dy, fo, B(s->d_ws, s->w_h2), w, r, G + s->off_w[2], stream);
   float* cs = reinterpret_cast<float*>(B(s->d_ws, s->w_cs));
   if (st == FKS_OK) st = check_hip(fks::launch_colsum(dy, r, fo, G + s->off_b[2], cs, kColsumBlocks, stream), "db3");
-  // dZ2: K = n^3 is long and M x N = batch x width has few tiles: split K
-  if (st == FKS_OK)
-    st = check_hip(fks::launch_gemm_dsilu_splitk(dy, W16 + 2 * s->off_w[2], r, w, fo, fo, w,
+  // dZ2: K = n^3 is long and M x N = batch x width has few tiles: split K.  Where the
+  // large-tile kernel applies, W3 is first transposed to [width][n^3] so that both operands
+  // are K-contiguous
+  if (st == FKS_OK && r % 256 == 0 && w % 256 == 0) {
+    void* w3t = B(s->d_ws, s->w_w3t);
+    st = check_hip(fks::launch_transpose_bf16(W16 + 2 * s->off_w[2], fo, w, w3t, stream), "W3 transpose");
+    if (st == FKS_OK)
+      st = check_hip(fks::launch_gemm_dsilu_splitk(dy, w3t, 0, r, w, fo, fo, fo,
+                                                   reinterpret_cast<const float*>(B(s->d_ws, s->w_z2)),
+                                                   B(s->d_ws, s->w_dz2), s->splits,
+                                                   reinterpret_cast<float*>(B(s->d_ws, s->w_sk)), stream),
+                     "dZ2");
+  } else if (st == FKS_OK) {
+    st = check_hip(fks::launch_gemm_dsilu_splitk(dy, W16 + 2 * s->off_w[2], 1, r, w, fo, fo, w,
                                                  reinterpret_cast<const float*>(B(s->d_ws, s->w_z2)),
                                                  B(s->d_ws, s->w_dz2), s->splits,
                                                  reinterpret_cast<float*>(B(s->d_ws, s->w_sk)), stream),
                    "dZ2");
+  }
   // layer 2
   if (st == FKS_OK) st = weight_grad(s, B(s->d_ws, s->w_dz2), w, B(s->d_ws, s->w_h1), w, r, G + s->off_w[1], stream);
   if (st == FKS_OK)
@@ -949,14 +962,15 @@ fks_status fks_sur_create(int32_t n, int32_t modes, int32_t width, int64_t max_b
   const size_t tmax = fo > w ? (fo > fi ? fo : fi) : (w > fi ? w : fi);
   s->w_ta = wb;   wb = round256(wb + 2 * Bm * tmax);
   s->w_tb = wb;   wb = round256(wb + 2 * Bm * (w > fi ? w : fi));
-  // largest split count <= 16 whose K range is a whole number of 32-wide GEMM k steps
+  // largest split count <= 16 whose K range is a whole number of GEMM k steps
   s->splits = 1;
   for (int sp = 16; sp > 1; --sp)
-    if (fo % (32 * size_t(sp)) == 0) {
+    if (fo % (size_t(fks::kGemmKStep) * sp) == 0) {
       s->splits = sp;
       break;
     }
   s->w_sk = wb;   wb = round256(wb + 4 * size_t(s->splits) * Bm * w);
+  s->w_w3t = wb;  wb = round256(wb + 2 * fo * w);  // W3 transposed ([width][n^3] bf16)
   s->ws_bytes = wb;
   *out = s;
   return ok();
@@ -1085,13 +1099,8 @@ fks_status fks_sur_forward(fks_sur s, const void* x, float* y, int64_t batch, vo
   if (st != FKS_OK) return st;
   if (!x || !y || batch < 128 || batch % 128 || batch > s->max_batch)
     return fail(FKS_E_ARG, "batch must be a multiple of 128 up to max_batch");
-  st = sur_forward(s, x, batch, stream);
-  if (st != FKS_OK) return st;
-  return check_hip(hipMemcpyAsync(y, B(s->d_ws, s->w_y), size_t(4) * batch * s->fout, hipMemcpyDeviceToDevice,
-                                  static_cast<hipStream_t>(stream)),
-                   "copy y") == FKS_OK
-             ? ok()
-             : FKS_E_DEVICE;
+  st = sur_forward(s, x, batch, stream, y);
+  return st == FKS_OK ? ok() : st;
 }
 
 fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t batch, float lr, int32_t update,

@@ -65,6 +65,7 @@ hipError_t launch_forward(int dtype_is_f32, int n, const void* f, void* fhat, vo
                           void* stream);
 
 // surrogate kernels
+constexpr int kGemmKStep = 64;  // k extent of one GEMM tile step (split-K ranges are multiples)
 enum { kEpiF32_ = 0, kEpiBiasSilu_ = 1, kEpiDSilu_ = 2, kEpiBiasBf16_ = 3 };
 hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B, int M, int N, int K, int lda,
                        int ldb, const float* bias, float* Cf, void* Ch, const float* Zin, int ldc, void* stream);
@@ -73,7 +74,7 @@ hipError_t launch_sum_partials(const double* partial, int n, double* out, void* 
 hipError_t launch_transpose_bf16(const void* in, int rows, int cols, void* out, void* stream);
 hipError_t launch_colsum(const void* X, int rows, int cols, float* out, float* partial, int max_blocks,
                          void* stream);
-hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int M, int N, int K, int lda, int ldb,
+hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int b_kn, int M, int N, int K, int lda, int ldb,
                                    const float* Zin, void* Ch, int splits, float* partial, void* stream);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, void* stream);

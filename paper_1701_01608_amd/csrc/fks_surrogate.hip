@@ -6,9 +6,9 @@
 // GEMM: C[M x N] = A[M x K] . B[K x N] on v_mfma_f32_32x32x16_bf16.  Operand layouts:
 // A is "MK" (row-major, K contiguous) or "KM" (K rows, M contiguous); B is "NK" (each of
 // the N columns stored K-contiguous, i.e. weights [out][in]) or "KN".  Tiles of 128 x 128
-// x 32 are staged through LDS K-contiguous, so one kernel serves the forward product
+// x 64 are staged through LDS K-contiguous, so one kernel serves the forward product
 // (A=MK, B=NK), the input gradient (A=MK, B=KN) and the weight gradient (A=KM, B=KN).
-// M, N, K must be multiples of 128, 128 and 32.
+// M, N, K must be multiples of 128, 128 and 64.
 #include <hip/hip_runtime.h>
 
 #include "fks_fft.hpp"
@@ -18,8 +18,10 @@ namespace fks {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 8, GLD = GBK + GPAD;  // LDS row stride (bf16)
+constexpr int GBM = 128, GBN = 128, GBK = kGemmKStep, GPAD = 8, GLD = GBK + GPAD;  // LDS row stride (bf16)
+static_assert(GBK == 64, "the tile loads below move 32 bf16 of A and of B per thread and k step");
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu_f(float z) {
@@ -35,6 +37,32 @@ enum GemmEpi {
   kEpiBiasBf16 = 3,   // Ch = bf16(acc + bias)
   kEpiPartial = 4     // split K: Cf[blockIdx.z][M][ldc] = partial acc
 };
+
+// epilogue of one 32 x 32 accumulator tile: lane holds rows row0 + 8 (e/4) + 4 (lane/32) +
+// e%4 (e < 16) of column col
+template <int EPI>
+__device__ __forceinline__ void gemm_store_tile(const f32x16& a, int row0, int col, int lane,
+                                                const float* __restrict__ bias, float* __restrict__ Cf,
+                                                __bf16* __restrict__ Ch, const float* __restrict__ Zin, int ldc) {
+  const float bv = (bias && EPI != kEpiDSilu && EPI != kEpiPartial) ? bias[col] : 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = row0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    const size_t o = size_t(row) * ldc + col;
+    const float v = a[e];
+    if constexpr (EPI == kEpiF32 || EPI == kEpiPartial) {
+      Cf[o] = v + bv;
+    } else if constexpr (EPI == kEpiBiasSilu) {
+      const float z = v + bv;
+      Cf[o] = z;
+      Ch[o] = __bf16(silu_f(z));
+    } else if constexpr (EPI == kEpiDSilu) {
+      Ch[o] = __bf16(v * dsilu_f(Zin[o]));
+    } else {
+      Ch[o] = __bf16(v + bv);
+    }
+  }
+}
 
 template <bool A_KM, bool B_KN, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, const __bf16* __restrict__ B, int M,
@@ -57,27 +85,39 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
   const int kb = blockIdx.z * k_split, ke = kb + k_split < K ? kb + k_split : K;
   if constexpr (EPI == kEpiPartial) Cf += size_t(blockIdx.z) * M * ldc;
 
-  // per-thread share of one k tile: 2 x 16 bytes of A and of B (named registers: no
+  // per-thread share of one k tile: 4 x 16 bytes of A and of B (named registers: no
   // address is taken, so nothing goes to private memory)
-  uint4 ra0, ra1, rb0, rb1;
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  // K-contiguous operand: row tid/2, 32 consecutive k; M- or N-contiguous operand: k rows
+  // tid/8 and tid/8 + 32, 16 consecutive columns each
   auto load_tile = [&](int k0) {
     if constexpr (!A_KM) {
-      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(m0 + (tid >> 1)) * lda + k0 + (tid & 1) * 16);
+      const uint4* src = reinterpret_cast<const uint4*>(A + size_t(m0 + (tid >> 1)) * lda + k0 + (tid & 1) * 32);
       ra0 = src[0];
       ra1 = src[1];
+      ra2 = src[2];
+      ra3 = src[3];
     } else {
       const uint4* src = reinterpret_cast<const uint4*>(A + size_t(k0 + (tid >> 3)) * lda + m0 + (tid & 7) * 16);
+      const uint4* src2 = reinterpret_cast<const uint4*>(A + size_t(k0 + 32 + (tid >> 3)) * lda + m0 + (tid & 7) * 16);
       ra0 = src[0];
       ra1 = src[1];
+      ra2 = src2[0];
+      ra3 = src2[1];
     }
     if constexpr (!B_KN) {
-      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(n0 + (tid >> 1)) * ldb + k0 + (tid & 1) * 16);
+      const uint4* src = reinterpret_cast<const uint4*>(B + size_t(n0 + (tid >> 1)) * ldb + k0 + (tid & 1) * 32);
       rb0 = src[0];
       rb1 = src[1];
+      rb2 = src[2];
+      rb3 = src[3];
     } else {
       const uint4* src = reinterpret_cast<const uint4*>(B + size_t(k0 + (tid >> 3)) * ldb + n0 + (tid & 7) * 16);
+      const uint4* src2 = reinterpret_cast<const uint4*>(B + size_t(k0 + 32 + (tid >> 3)) * ldb + n0 + (tid & 7) * 16);
       rb0 = src[0];
       rb1 = src[1];
+      rb2 = src2[0];
+      rb3 = src2[1];
     }
   };
   // 16 consecutive bf16 of one k row scattered to 16 rows of a K-contiguous tile
@@ -92,18 +132,26 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
   // LDS tiles K-contiguous: As[m][k], Bs[n][k]
   auto store_tile = [&](int buf) {
     if constexpr (!A_KM) {
-      uint4* dst = reinterpret_cast<uint4*>(As[buf] + (tid >> 1) * GLD + (tid & 1) * 16);
+      uint4* dst = reinterpret_cast<uint4*>(As[buf] + (tid >> 1) * GLD + (tid & 1) * 32);
       dst[0] = ra0;
       dst[1] = ra1;
+      dst[2] = ra2;
+      dst[3] = ra3;
     } else {
-      scatter16(reinterpret_cast<unsigned short*>(As[buf]), (tid & 7) * 16, tid >> 3, ra0, ra1);
+      unsigned short* t = reinterpret_cast<unsigned short*>(As[buf]);
+      scatter16(t, (tid & 7) * 16, tid >> 3, ra0, ra1);
+      scatter16(t, (tid & 7) * 16, 32 + (tid >> 3), ra2, ra3);
     }
     if constexpr (!B_KN) {
-      uint4* dst = reinterpret_cast<uint4*>(Bs[buf] + (tid >> 1) * GLD + (tid & 1) * 16);
+      uint4* dst = reinterpret_cast<uint4*>(Bs[buf] + (tid >> 1) * GLD + (tid & 1) * 32);
       dst[0] = rb0;
       dst[1] = rb1;
+      dst[2] = rb2;
+      dst[3] = rb3;
     } else {
-      scatter16(reinterpret_cast<unsigned short*>(Bs[buf]), (tid & 7) * 16, tid >> 3, rb0, rb1);
+      unsigned short* t = reinterpret_cast<unsigned short*>(Bs[buf]);
+      scatter16(t, (tid & 7) * 16, tid >> 3, rb0, rb1);
+      scatter16(t, (tid & 7) * 16, 32 + (tid >> 3), rb2, rb3);
     }
   };
 
@@ -133,31 +181,126 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
     __syncthreads();
     cur ^= 1;
   }
-  // ---- epilogue: lane holds rows 8*(e/4) + 4*(lane/32) + e%4, column lane%32 of each tile
+  // ---- epilogue
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn + j * 32 + (lane & 31);
-      const float bv = (bias && EPI != kEpiDSilu && EPI != kEpiPartial) ? bias[col] : 0.0f;
+    for (int j = 0; j < 2; ++j)
+      gemm_store_tile<EPI>(acc[i][j], m0 + wm + i * 32, n0 + wn + j * 32 + (lane & 31), lane, bias, Cf, Ch, Zin, ldc);
+}
+
+// Large-tile GEMM for K-contiguous A and B (A = MK, B = NK): 256 x 256 x 64 block tiles,
+// four waves of 128 x 128 (sixteen 32 x 32 accumulators each), two LDS stages of 72 KiB.
+// Each block moves 64 KiB per k step for 8.4 MFLOP (128 flop per byte from L2, twice the
+// 128 x 128 tile), which the large products of the output layer need.  M, N multiples of
+// 256, K (and the split-K range) multiples of 64.
+constexpr int BBM = 256, BBN = 256;
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_big(const __bf16* __restrict__ A, const __bf16* __restrict__ B, int M,
+                                                  int N, int K, int lda, int ldb, const float* __restrict__ bias,
+                                                  float* __restrict__ Cf, __bf16* __restrict__ Ch,
+                                                  const float* __restrict__ Zin, int ldc, int k_split) {
+  __shared__ __align__(16) __bf16 smem[2][(BBM + BBN) * GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BBM, n0 = blockIdx.x * BBN;
+  const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+  f32x16 acc[4][4];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        const size_t o = size_t(row) * ldc + col;
-        const float v = acc[i][j][e];
-        if constexpr (EPI == kEpiF32 || EPI == kEpiPartial) {
-          Cf[o] = v + bv;
-        } else if constexpr (EPI == kEpiBiasSilu) {
-          const float z = v + bv;
-          Cf[o] = z;
-          Ch[o] = __bf16(silu_f(z));
-        } else if constexpr (EPI == kEpiDSilu) {
-          Ch[o] = __bf16(v * dsilu_f(Zin[o]));
-        } else {
-          Ch[o] = __bf16(v + bv);
-        }
-      }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+  const int kb = blockIdx.z * k_split, ke = kb + k_split < K ? kb + k_split : K;
+  if constexpr (EPI == kEpiPartial) Cf += size_t(blockIdx.z) * M * ldc;
+
+  // per thread and k step: rows tid/8 + 32 j (j < 8) of A and of B, 8 bf16 at k offset 8 (tid%8);
+  // the staging arrays are indexed by compile-time constants only, so they stay in registers
+  u32x4 ra[8], rb[8];
+  // uniform row bases plus one 32-bit lane offset per operand (scalar-base addressing)
+  const unsigned va = unsigned(((tid >> 3) * lda + (tid & 7) * 8) * 2);
+  const unsigned vb = unsigned(((tid >> 3) * ldb + (tid & 7) * 8) * 2);
+  const int st_off = (tid >> 3) * GLD + (tid & 7) * 8;
+#define GEMM_BIG_LOAD(k0)                                                                        \
+  static_for<0, 8>([&](auto jj) {                                                                \
+    constexpr int j = decltype(jj)::value;                                                       \
+    const char* a_row = reinterpret_cast<const char*>(A + size_t(m0 + 32 * j) * lda + (k0));     \
+    const char* b_row = reinterpret_cast<const char*>(B + size_t(n0 + 32 * j) * ldb + (k0));     \
+    ra[j] = *reinterpret_cast<const u32x4*>(a_row + va);                                         \
+    rb[j] = *reinterpret_cast<const u32x4*>(b_row + vb);                                         \
+  });
+#define GEMM_BIG_STORE(buf)                                                             \
+  static_for<0, 8>([&](auto jj) {                                                       \
+    constexpr int j = decltype(jj)::value;                                              \
+    *reinterpret_cast<u32x4*>(smem[buf] + st_off + 32 * j * GLD) = ra[j];               \
+    *reinterpret_cast<u32x4*>(smem[buf] + BBM * GLD + st_off + 32 * j * GLD) = rb[j];   \
+  });
+
+  if (kb < ke) {
+    GEMM_BIG_LOAD(kb)
+    GEMM_BIG_STORE(0)
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    if (k0 + GBK < ke) {
+      GEMM_BIG_LOAD(k0 + GBK)
     }
+    sched_fence();
+    const __bf16* As = smem[cur] + (wm + (lane & 31)) * GLD + 8 * (lane >> 5);
+    const __bf16* Bs = smem[cur] + BBM * GLD + (wn + (lane & 31)) * GLD + 8 * (lane >> 5);
+    // fragments double-buffered in registers: the reads of k sub-step q + 1 are issued
+    // between the sixteen products of sub-step q (one read per two products); during the
+    // last sub-step the staged next tile is written to the other LDS stage instead (also
+    // after the final tile, where it rewrites data nobody reads: no branch in the schedule)
+    bf16x8 fa[2][4], fb[2][4];
+    static_for<0, 4>([&](auto ii) {
+      constexpr int r = decltype(ii)::value;
+      fa[0][r] = *reinterpret_cast<const bf16x8*>(As + r * 32 * GLD);
+      fb[0][r] = *reinterpret_cast<const bf16x8*>(Bs + r * 32 * GLD);
+    });
+    static_for<0, GBK / 16>([&](auto qq) {
+      constexpr int q = decltype(qq)::value, c = q & 1;
+      if constexpr (q + 1 < GBK / 16) {
+        static_for<0, 4>([&](auto ii) {
+          constexpr int r = decltype(ii)::value;
+          fa[c ^ 1][r] = *reinterpret_cast<const bf16x8*>(As + r * 32 * GLD + (q + 1) * 16);
+          fb[c ^ 1][r] = *reinterpret_cast<const bf16x8*>(Bs + r * 32 * GLD + (q + 1) * 16);
+        });
+      } else {
+        GEMM_BIG_STORE(cur ^ 1)
+      }
+      static_for<0, 4>([&](auto ii) {
+        static_for<0, 4>([&](auto jj) {
+          constexpr int r = decltype(ii)::value, t = decltype(jj)::value;
+          acc[r][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c][r], fb[c][t], acc[r][t], 0, 0, 0);
+        });
+      });
+      if constexpr (q + 1 < GBK / 16) {
+        static_for<0, 8>([&](auto) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMA
+        });
+      } else {
+        static_for<0, 16>([&](auto) {
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS write
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        });
+      }
+      sched_fence();
+    });
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef GEMM_BIG_LOAD
+#undef GEMM_BIG_STORE
+  static_for<0, 4>([&](auto ii) {
+    static_for<0, 4>([&](auto jj) {
+      constexpr int r = decltype(ii)::value, t = decltype(jj)::value;
+      gemm_store_tile<EPI>(acc[r][t], m0 + wm + r * 32, n0 + wn + t * 32 + (lane & 31), lane, bias, Cf, Ch, Zin, ldc);
+      sched_fence();  // one accumulator tile at a time: bounded register use
+    });
+  });
 }
 
 // split-K reduction with the input-gradient epilogue: Ch = bf16(sum_z P[z] * silu'(Zin))
@@ -721,6 +864,17 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
                        Zin, ldc, K);                                                                     \
     return hipGetLastError();                                                                            \
   }
+  // large K-contiguous products with enough 256 x 256 tiles to fill the chip
+  if (!a_km && !b_kn && M % BBM == 0 && N % BBN == 0 && int64_t(M / BBM) * (N / BBN) >= 256 &&
+      (epi == kEpiF32 || epi == kEpiBiasBf16)) {
+    const dim3 gb(N / BBN, M / BBM);
+    if (epi == kEpiF32)
+      hipLaunchKernelGGL((k_gemm_big<kEpiF32>), gb, dim3(256), 0, st, a, b, M, N, K, lda, ldb, bias, Cf, ch, Zin, ldc, K);
+    else
+      hipLaunchKernelGGL((k_gemm_big<kEpiBiasBf16>), gb, dim3(256), 0, st, a, b, M, N, K, lda, ldb, bias, Cf, ch, Zin,
+                         ldc, K);
+    return hipGetLastError();
+  }
   GEMM_CASE(false, false, kEpiF32)
   GEMM_CASE(false, false, kEpiBiasSilu)
   GEMM_CASE(false, false, kEpiBiasBf16)
@@ -731,13 +885,22 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int M, int N, int K, int lda, int ldb,
+// split-K product A [M][K] (MK) . B with B "KN" ([K][N]) or, b_kn = 0, "NK" ([N][K]; then M
+// and N must be multiples of 256 for the large-tile kernel), reduced with the SiLU' epilogue
+hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int b_kn, int M, int N, int K, int lda, int ldb,
                                    const float* Zin, void* Ch, int splits, float* partial, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int k_split = K / splits;
-  hipLaunchKernelGGL((k_gemm<false, true, kEpiPartial>), dim3(N / GBN, M / GBM, splits), dim3(256), 0, st,
-                     static_cast<const __bf16*>(A), static_cast<const __bf16*>(B), M, N, K, lda, ldb,
-                     static_cast<const float*>(nullptr), partial, static_cast<__bf16*>(nullptr), Zin, N, k_split);
+  if (b_kn) {
+    hipLaunchKernelGGL((k_gemm<false, true, kEpiPartial>), dim3(N / GBN, M / GBM, splits), dim3(256), 0, st,
+                       static_cast<const __bf16*>(A), static_cast<const __bf16*>(B), M, N, K, lda, ldb,
+                       static_cast<const float*>(nullptr), partial, static_cast<__bf16*>(nullptr), Zin, N, k_split);
+  } else {
+    if (M % BBM || N % BBN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gemm_big<kEpiPartial>), dim3(N / BBN, M / BBM, splits), dim3(256), 0, st,
+                       static_cast<const __bf16*>(A), static_cast<const __bf16*>(B), M, N, K, lda, ldb,
+                       static_cast<const float*>(nullptr), partial, static_cast<__bf16*>(nullptr), Zin, N, k_split);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t mn = int64_t(M) * N;

@@ -26,10 +26,10 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _tiny(seed=5, width=128):
+def _tiny(seed=5, width=128, n=8, modes=4, max_batch=256):
     import paper_1701_01608_amd as fks
     from oracle import mlp
-    sur = fks.Surrogate(n=8, modes=4, width=width, max_batch=256)
+    sur = fks.Surrogate(n=n, modes=modes, width=width, max_batch=max_batch)
     params = mlp.init_params([sur.n_in, width, width, sur.n_out], seed)
     rng = np.random.default_rng(seed + 100)
     params[1] = rng.normal(0, 0.1, params[1].shape)
@@ -76,6 +76,34 @@ def test_gradients_match_oracle():
     p_after = sur.get_params()
     for a, b in zip(p_after, params):
         assert np.array_equal(a, np.asarray(b, dtype=np.float32))
+
+
+def test_large_tile_products_match_oracle():
+    """The 256 x 256 tile products: output layer forward at batch 512 (2 x 128 tiles), its
+    weight gradient (n^3 x width = 128 x 2 tiles) and the split-K input gradient through
+    the transposed W3 (batch and width multiples of 256)."""
+    from oracle import mlp
+    sur, params = _tiny(seed=31, width=512, n=32, modes=8, max_batch=512)
+    rng = np.random.default_rng(131)
+    x = rng.standard_normal((512, sur.n_in))
+    xd = torch.as_tensor(x, dtype=torch.float32).to(torch.bfloat16).cuda()
+    y = sur.forward(xd).cpu().numpy()
+    pr = [_bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
+    y_ref, _ = mlp.forward(pr, _bf16_round(x))
+    err = _rel(y, y_ref)
+    print(f"forward rel-L2 {err:.3e}")
+    assert err <= 1e-2
+    t = rng.standard_normal((256, sur.n_out)) * 0.5
+    td = torch.as_tensor(t, dtype=torch.float32).cuda()
+    loss = sur.train_step(xd[:256].contiguous(), td, lr=0.0, update=False)
+    torch.cuda.synchronize()
+    g = sur.get_grads()
+    loss_ref, g_ref = mlp.loss_and_grads(pr, _bf16_round(x[:256]), t)
+    assert abs(loss.item() - loss_ref) <= 1e-2 * loss_ref
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], g, g_ref):
+        err = _rel(a, b)
+        print(f"grad {name} rel-L2 {err:.3e}")
+        assert err <= 3e-2, name
 
 
 def test_adam_step_matches_oracle():
