@@ -473,8 +473,11 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ f, __bf1
                                                   int center, double L) {
   constexpr int M = 2 * MH;
   static_assert(MH <= N / 2 - 1, "modes beyond the kept set");
-  __shared__ cpx<float> zs[N * N][M];     // z partials [x][y][kz + MH]
-  __shared__ cpx<float> ys[N][M][M];      // y partials [x][ky + MH][kz + MH]
+  static_assert(N * M <= 256, "one y line per thread");
+  static_assert(M * M <= N * (MH + 1), "y partials fit in the z partials' storage");
+  __shared__ cpx<float> zs[N * N][MH + 1];  // z partials [x][y][kz], kz = 0..MH (negative kz: conjugates)
+  // y partials [x][ky + MH][kz + MH], in the same storage once every z partial has been read
+  cpx<float>(*ys)[M][M] = reinterpret_cast<cpx<float>(*)[M][M]>(&zs[0][0]);
   __shared__ double red[5 * 16];
   const int cell = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const T* fc = f + size_t(cell) * N * N * N;
@@ -510,28 +513,31 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ f, __bf1
         if constexpr (w.c != 0.0) re += float(w.c) * float(r[z]);
         if constexpr (w.s != 0.0) im += float(w.s) * float(r[z]);
       });
-      if constexpr (k < MH) zs[row][MH + k] = cpx<float>{re, im};
-      if constexpr (k > 0) zs[row][MH - k] = cpx<float>{re, -im};
+      zs[row][k] = cpx<float>{re, im};
       sched_fence();
     });
   }
   // y pass: lines (x, kz)
   __syncthreads();
-  for (int it = tid; it < N * M; it += nt) {
-    const int x = it / M, kzi = it % M;
-    cpx<float> acc[M];
-    static_for<0, M>([&](auto k) { acc[k] = cpx<float>{0.0f, 0.0f}; });
+  cpx<float> acc[M];
+  static_for<0, M>([&](auto k) { acc[k] = cpx<float>{0.0f, 0.0f}; });
+  if (tid < N * M) {
+    const int x = tid / M, kzi = tid % M;
+    const int kz = kzi - MH, kza = kz < 0 ? -kz : kz;
+    const float cs = kz < 0 ? -1.0f : 1.0f;  // f real: the kz < 0 partial is the conjugate
     static_for<0, N>([&](auto yy) {
       constexpr int y = decltype(yy)::value;
-      const cpx<float> v = zs[x * N + y][kzi];
+      const cpx<float> zv = zs[x * N + y][kza];
+      const cpx<float> v = {zv.re, cs * zv.im};
       static_for<0, M>([&](auto kk) {
         constexpr sc w = sincos2pi(-long(decltype(kk)::value - MH) * y, N);
         acc[kk] = acc[kk] + cmul(v, cpx<float>{float(w.c), float(w.s)});
       });
       if constexpr (y % 8 == 7) sched_fence();
     });
-    static_for<0, M>([&](auto k) { ys[x][decltype(k)::value][kzi] = acc[k]; });
   }
+  __syncthreads();  // every z partial read: the storage now takes the y partials
+  if (tid < N * M) static_for<0, M>([&](auto k) { ys[tid / M][decltype(k)::value][tid % M] = acc[k]; });
   block_reduce_moments(m, red);
   __syncthreads();
   {
@@ -688,8 +694,11 @@ __device__ __forceinline__ void shift_line(float* r, const cpx<float>* ph) {
   cpx<float> z[M];
   static_for<0, M>([&](auto k) {
     constexpr int kk = decltype(k)::value;
-    const cpx<float> xk = kk == 0 ? cpx<float>{o[0].re, 0.0f} : o[kk];
-    const cpx<float> xm = kk == 0 ? cpx<float>{0.0f, 0.0f} : conj(o[M - kk]);  // X_{M-k}, X_M = 0
+    cpx<float> xk = {o[0].re, 0.0f}, xm = {0.0f, 0.0f};  // X_k and conj X_{M-k}, X_M = 0
+    if constexpr (kk > 0) {
+      xk = o[kk];
+      xm = conj(o[M - kk]);
+    }
     const cpx<float> sp = xk + xm, dm = twiddle<N, +1, kk>(xk - xm);
     z[kk] = cpx<float>{sp.re - dm.im, sp.im + dm.re};
   });
@@ -725,18 +734,33 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
     ph[i] = cpx<float>{float(cs / N), float(sn / N)};
   }
   __syncthreads();
-  // z pass straight from global memory: row (x, y) is N contiguous floats
-  const float* ic = in + size_t(cell) * ld_in;
+  // the cell into LDS by coalesced 16-byte loads (consecutive lanes, consecutive float4;
+  // all of a thread's loads in flight at once), rows (x, y) of N floats at stride RS
+  const float4* ic4 = reinterpret_cast<const float4*>(in + size_t(cell) * ld_in);
+  constexpr int NV = N * N * N / 4;  // float4 per cell
+  constexpr int NR = (NV + SL::TPB - 1) / SL::TPB;  // rounds (the last may be partial)
+  {
+    float4 v[NR];
+    static_for<0, NR>([&](auto q) {
+      const int i = tid + decltype(q)::value * SL::TPB;
+      if (NV % SL::TPB == 0 || i < NV) v[q] = ic4[i];
+    });
+    static_for<0, NR>([&](auto q) {
+      const int i = tid + decltype(q)::value * SL::TPB, row = i / (N / 4), col = 4 * (i % (N / 4));
+      if (NV % SL::TPB == 0 || i < NV) {
+        float* d = sm + row * RS + col;
+        d[0] = v[q].x * mult;
+        d[1] = v[q].y * mult;
+        d[2] = v[q].z * mult;
+        d[3] = v[q].w * mult;
+      }
+    });
+  }
+  __syncthreads();
+  // z pass in LDS: row (x, y), in place (each row belongs to one thread)
   for (int line = tid; line < N * N; line += nt) {
     float r[N];
-    const float4* src = reinterpret_cast<const float4*>(ic + size_t(line) * N);
-    static_for<0, N / 4>([&](auto q) {
-      const float4 v = src[decltype(q)::value];
-      r[4 * decltype(q)::value] = v.x * mult;
-      r[4 * decltype(q)::value + 1] = v.y * mult;
-      r[4 * decltype(q)::value + 2] = v.z * mult;
-      r[4 * decltype(q)::value + 3] = v.w * mult;
-    });
+    static_for<0, N>([&](auto j) { r[j] = sm[line * RS + decltype(j)::value]; });
     shift_line<N>(r, ph + 2 * KH1);
     static_for<0, N>([&](auto j) { sm[line * RS + decltype(j)::value] = r[j]; });
   }
