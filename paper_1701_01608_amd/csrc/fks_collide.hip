@@ -104,17 +104,6 @@ __device__ __forceinline__ cpx<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff
   }
 }
 
-// exp(2 pi i q / S) for a runtime q in [0, S), from literals
-template <int S>
-__device__ __forceinline__ sc chunk_twiddle(int q) {
-  sc w = {1.0, 0.0};
-  static_for<1, S>([&](auto qq) {
-    constexpr sc c = sincos2pi(decltype(qq)::value, S);
-    if (q == decltype(qq)::value) w = c;
-  });
-  return w;
-}
-
 __device__ __forceinline__ int opaque_tid() {
   int t = threadIdx.x;
   asm volatile("" : "+v"(t));
@@ -290,91 +279,126 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   // and mode -k_z of (-kx, -ky) come from the same stored value (Hermitian fhat, even
   // tables).  Rows are taken in chunks j of Z consecutive modes; with k_z = jZ + b - N/2
   // the slab twiddle exp(2 pi i k_z r/P) = w_S^{jr} exp(2 pi i (b - N/2) r/P): the chunk
-  // factor is one runtime scalar, the per-bin factor is applied once after the loop.
-  // Output: the Z planes [z'][kx + Kh][ky + Kh] of dst with row stride `ld`.
-  auto stage1 = [&](int t, cpx<T>* dst, auto ld_c) {
-    constexpr int LD = decltype(ld_c)::value;
-    const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
-    // Every stage takes an opaque copy of the thread index (opaque_tid): its index
-    // arithmetic is redone where it is used instead of being hoisted out of the term
-    // loop or shared between stages and kept live next to the accumulator (LDS plane
-    // offsets beyond the 64 KiB immediate range need their own address registers).
-    const int tid = opaque_tid();
-    for (int p = tid; p < NPAIR; p += NT) {
-      int kx, ky;
-      pair_kxy<K, Kh>(p, kx, ky);
-      // With g = w f (w the chunk twiddle) and the real table pair (a, b), the pencil
-      // accumulates (a + ib) g and its mirror conj((a - ib) g); both come from the four
-      // real sums s1 = sum a Re g, s2 = sum b Im g, s3 = sum a Im g, s4 = sum b Re g:
-      // A = (s1 - s2, s3 + s4), B = (s1 + s2, s4 - s3).
-      T s1[Z], s2[Z], s3[Z], s4[Z];
-      static_for<0, Z>([&](auto bb) {
-        s1[bb] = T(0);
-        s2[bb] = T(0);
-        s3[bb] = T(0);
-        s4[bb] = T(0);
-      });
-      const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
-      // software pipeline over half chunks: the loads of the next half chunk are in
-      // flight while the current one is accumulated
-      constexpr int ZH = (Z + 1) / 2;
-      cpx<T> pf0[ZH], pa0[ZH], pf1[ZH], pa1[ZH];
-      auto load_half = [&](cpx<T>* pf, cpx<T>* pa, int j, auto half) {
-        constexpr int b0 = decltype(half)::value * ZH;
-        const uint32_t s0 = uint32_t(j) * Z * row_bytes;
-        static_for<0, ZH>([&](auto i) {
-          constexpr int bb = b0 + decltype(i)::value;
-          if constexpr (bb < Z) {
-            pf[i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
-            pa[i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
-          }
-        });
-      };
-      auto accumulate = [&](const cpx<T>* pf, const cpx<T>* pa, T cr, T ci, auto half) {
-        constexpr int b0 = decltype(half)::value * ZH;
-        static_for<0, ZH>([&](auto i) {
-          constexpr int bb = b0 + decltype(i)::value;
-          if constexpr (bb < Z) {
-            const cpx<T> fv = pf[i], ab = pa[i];
-            const T gr = cr * fv.re - ci * fv.im, gi = cr * fv.im + ci * fv.re;
-            s1[bb] += ab.re * gr;
-            s2[bb] += ab.im * gi;
-            s3[bb] += ab.re * gi;
-            s4[bb] += ab.im * gr;
-          }
-        });
-      };
-      using H0 = std::integral_constant<int, 0>;
-      using H1 = std::integral_constant<int, 1>;
-      load_half(pf0, pa0, 0, H0{});
-#pragma unroll 1
-      for (int j = 0; j < C::NCH; ++j) {
-        const sc wj = chunk_twiddle<C::S>((j * RID) % C::S);
-        const T cr = T(wj.c), ci = T(wj.s);
-        load_half(pf1, pa1, j, H1{});
-        accumulate(pf0, pa0, cr, ci, H0{});
-        if (j + 1 < C::NCH) load_half(pf0, pa0, j + 1, H0{});
-        accumulate(pf1, pa1, cr, ci, H1{});
+  // factor w_S^{jr} is a compile-time constant (for most (j, r) it is +-1, always at
+  // j = 0 and r = 0, and its complex product folds away), the per-bin factor is applied
+  // once after the last chunk.  Output: the Z planes [z'][kx + Kh][ky + Kh] of dst with
+  // row stride `ld`.
+  //
+  // The rows are streamed through a two-deep software pipeline of half chunks: the loads
+  // of the next half chunk are in flight while the current one is accumulated.  The
+  // pipeline is primed (stage1_issue: both halves of chunk 0) before `mid` runs and
+  // drained after it (stage1_finish), so that independent work placed in `mid` hides the
+  // latency of the first loads.
+  constexpr int ZH = (Z + 1) / 2;
+  using H0 = std::integral_constant<int, 0>;
+  using H1 = std::integral_constant<int, 1>;
+  struct Pipe {
+    cpx<T> pf0[ZH], pa0[ZH], pf1[ZH], pa1[ZH];
+  };
+  auto load_half = [&](cpx<T>* pf, cpx<T>* pa, uint32_t voff, uint32_t tterm, auto jc, auto half) {
+    constexpr int b0 = decltype(half)::value * ZH;
+    constexpr uint32_t s0 = uint32_t(decltype(jc)::value) * Z * row_bytes;
+    static_for<0, ZH>([&](auto i) {
+      constexpr int bb = b0 + decltype(i)::value;
+      if constexpr (bb < Z) {
+        pf[i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
+        pa[i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
       }
-      // per-bin twiddles and the bin of each partial sum (k_z mod Z, resp. -k_z mod Z)
-      cpx<T> oA[Z], oB[Z];
-      static_for<0, Z>([&](auto bb) {
-        constexpr int e = decltype(bb)::value - N / 2;
-        const cpx<T> bA = {s1[bb] - s2[bb], s3[bb] + s4[bb]};
-        const cpx<T> bB = {s1[bb] + s2[bb], s4[bb] - s3[bb]};
-        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA);
-        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB);
+    });
+  };
+  auto stage1_issue = [&](Pipe& q, int p, int t) {
+    const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+    const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
+    using J0 = std::integral_constant<int, 0>;
+    load_half(q.pf0, q.pa0, voff, tterm, J0{}, H0{});
+    load_half(q.pf1, q.pa1, voff, tterm, J0{}, H1{});
+  };
+  auto stage1_finish = [&](Pipe& q, int p, int t, cpx<T>* dst, auto ld_c) {
+    constexpr int LD = decltype(ld_c)::value;
+    const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+    const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
+    int kx, ky;
+    pair_kxy<K, Kh>(p, kx, ky);
+    // With g = w f (w the chunk twiddle) and the real table pair (a, b), the pencil
+    // accumulates (a + ib) g and its mirror conj((a - ib) g); both come from the four
+    // real sums s1 = sum a Re g, s2 = sum b Im g, s3 = sum a Im g, s4 = sum b Re g:
+    // A = (s1 - s2, s3 + s4), B = (s1 + s2, s4 - s3).
+    T s1[Z], s2[Z], s3[Z], s4[Z];
+    static_for<0, Z>([&](auto bb) {
+      s1[bb] = T(0);
+      s2[bb] = T(0);
+      s3[bb] = T(0);
+      s4[bb] = T(0);
+    });
+    auto accumulate = [&](const cpx<T>* pf, const cpx<T>* pa, auto jc, auto half) {
+      constexpr int b0 = decltype(half)::value * ZH;
+      constexpr long qe = long(decltype(jc)::value) * RID;
+      static_for<0, ZH>([&](auto i) {
+        constexpr int bb = b0 + decltype(i)::value;
+        if constexpr (bb < Z) {
+          const cpx<T> ab = pa[i];
+          const cpx<T> g = twiddle<C::S, +1, qe>(pf[i]);
+          s1[bb] += ab.re * g.re;
+          s2[bb] += ab.im * g.im;
+          s3[bb] += ab.re * g.im;
+          s4[bb] += ab.im * g.re;
+        }
       });
-      dft<Z, +1>(oA);
-      const int kxa = kx + Kh, kya = ky + Kh;
-      static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxa) * LD + kya] = oA[zp]; });
-      if (kx != 0 || ky != 0) {
-        dft<Z, +1>(oB);
-        const int kxb = Kh - kx, kyb = Kh - ky;
-        static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxb) * LD + kyb] = oB[zp]; });
+    };
+    static_for<0, C::NCH>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      using JN = std::integral_constant<int, (j + 1 < C::NCH ? j + 1 : j)>;
+      // no load is hoisted past its half chunk (keeps the pipeline two deep)
+      sched_fence();
+      accumulate(q.pf0, q.pa0, jc, H0{});
+      if constexpr (j + 1 < C::NCH) load_half(q.pf0, q.pa0, voff, tterm, JN{}, H0{});
+      sched_fence();
+      accumulate(q.pf1, q.pa1, jc, H1{});
+      if constexpr (j + 1 < C::NCH) load_half(q.pf1, q.pa1, voff, tterm, JN{}, H1{});
+    });
+    // per-bin twiddles and the bin of each partial sum (k_z mod Z, resp. -k_z mod Z)
+    cpx<T> oA[Z], oB[Z];
+    static_for<0, Z>([&](auto bb) {
+      constexpr int e = decltype(bb)::value - N / 2;
+      const cpx<T> bA = {s1[bb] - s2[bb], s3[bb] + s4[bb]};
+      const cpx<T> bB = {s1[bb] + s2[bb], s4[bb] - s3[bb]};
+      oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA);
+      oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB);
+    });
+    dft<Z, +1>(oA);
+    const int kxa = kx + Kh, kya = ky + Kh;
+    static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxa) * LD + kya] = oA[zp]; });
+    if (kx != 0 || ky != 0) {
+      dft<Z, +1>(oB);
+      const int kxb = Kh - kx, kyb = Kh - ky;
+      static_for<0, Z>([&](auto zp) { dst[(size_t(zp) * K + kxb) * LD + kyb] = oB[zp]; });
+    }
+  };
+  // Every stage takes an opaque copy of the thread index (opaque_tid): its index
+  // arithmetic is redone where it is used instead of being hoisted out of the term loop
+  // or shared between stages and kept live next to the accumulator (LDS plane offsets
+  // beyond the 64 KiB immediate range need their own address registers).
+  auto stage1 = [&](int t, cpx<T>* dst, auto ld_c, auto&& mid) {
+    if constexpr (C::GREG) {
+      // one pencil per thread at most
+      static_assert(NPAIR <= NT, "FP32 schedules give every pencil its own thread");
+      const int p = opaque_tid();
+      Pipe q;
+      if (p < NPAIR) stage1_issue(q, p, t);
+      sched_fence();
+      mid();
+      sched_fence();
+      if (p < NPAIR) stage1_finish(q, p, t, dst, ld_c);
+    } else {
+      mid();
+      for (int p = opaque_tid(); p < NPAIR; p += NT) {
+        Pipe q;
+        stage1_issue(q, p, t);
+        stage1_finish(q, p, t, dst, ld_c);
       }
     }
   };
+  auto nothing = [] {};
 
   if constexpr (C::GREG) {
     // FP32: two LDS buffers.  X holds stage 1's output [Z][K][K]; W the y-transformed
@@ -383,7 +407,7 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     // so the waves waiting on stage 1's loads overlap with the others' x-line transforms.
     cpx<T>* X = W + C::w_elems;
     using LdX = std::integral_constant<int, K>;
-    if (t_begin < t_end) stage1(t_begin, X, LdX{});
+    if (t_begin < t_end) stage1(t_begin, X, LdX{}, nothing);
     __syncthreads();
     for (int t = t_begin; t < t_end; ++t) {
       // stage 2: y lines (z', kx): K modes -> P points; work item it = h*Z*K + line
@@ -404,9 +428,9 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
         }
       }
       __syncthreads();
-      if (t + 1 < t_end) stage1(t + 1, X, LdX{});
-      // stage 3: x lines (z', y): K modes -> P points, G += Re * Im
-      {
+      // stage 3: x lines (z', y): K modes -> P points, G += Re * Im; it runs between the
+      // first loads and the accumulation of stage 1 of term t + 1
+      auto stage3 = [&] {
         const int tid = opaque_tid();
         if (tid < 2 * C::LINES) {
           const int h = tid / C::LINES, line = tid - h * C::LINES;
@@ -418,13 +442,15 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
           dft<P / 2, +1>(u);
           static_for<0, P / 2>([&](auto j) { g[j] += u[j].re * u[j].im; });
         }
-      }
+      };
+      if (t + 1 < t_end) stage1(t + 1, X, LdX{}, stage3);
+      else stage3();
       __syncthreads();
     }
   } else {
     using LdW = std::integral_constant<int, WS>;
     for (int t = t_begin; t < t_end; ++t) {
-      stage1(t, W, LdW{});
+      stage1(t, W, LdW{}, nothing);
       __syncthreads();
       // stage 2: y lines (z', kx): K modes -> P points, in place
       {
