@@ -35,7 +35,12 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "4b45a8a8348add8f", "bytes": 2215124992}
+SLAB_TRAFFIC = {"sha": "0a83d09e20118c4d", "bytes": 2326638985}
+
+
+def progress(msg):
+    """One line on stderr per finished phase (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_hash():
@@ -192,7 +197,9 @@ def bench_surrogate(fks, torch, dev, train_seconds=60.0, infer_cells=32768, thre
             make_pairs(1_000_000 + c0, c, x_out=x_all[c0:c0 + c], t_out=t_all[c0:c0 + c])
         torch.cuda.synchronize()
     gen_wall = time.perf_counter() - t_gen
+    progress(f"surrogate training pairs ready ({gen_wall:.1f} s)")
     t_start = time.perf_counter()
+    next_report = 15.0
     steps, samples, rnd, last_loss = 0, 0, 0, None
     while True:
         if pairs:
@@ -211,6 +218,9 @@ def bench_surrogate(fks, torch, dev, train_seconds=60.0, infer_cells=32768, thre
             if pairs and steps % 64 == 0 and time.perf_counter() - t_start >= train_seconds:
                 break
         torch.cuda.synchronize()
+        if time.perf_counter() - t_start >= next_report:
+            progress(f"surrogate training: {steps} steps")
+            next_report += 15.0
         if time.perf_counter() - t_start >= train_seconds:
             last_loss = loss.item()
             break
@@ -349,6 +359,7 @@ def main():
     cpu, oracle_q = None, None
     if not args.no_cpu:
         cpu, oracle_q = cpu_baseline(f64[:512].astype(np.float32))
+        progress(f"cpu baseline done: {cpu['value']:.3e} cells*N^3/s on {cpu['cores']} cores")
 
     import paper_1701_01608_amd as fks
     dev = torch.device("cuda:0")
@@ -370,6 +381,7 @@ def main():
     prof = fks.profile_stop()
     ms_step = wall * 1e3 / args.steps
     value = CELLS * N ** 3 / (wall / args.steps)
+    progress(f"fp32 batch done: {ms_step:.3f} ms per step")
 
     # accuracy: against the FP64 oracle's Q of the cells the CPU baseline computed, and
     # against the GPU FP64 path (itself pinned to the oracle by the tests) on every cell
@@ -422,11 +434,15 @@ def main():
         if oracle_q is not None:
             out["f64_path"]["rel_l2"], _ = rel_vs_oracle(qd)
         del plan64, fd, qd
+        progress(f"fp64 batch done: {w64 * 1e3:.3f} ms per step")
 
     if not args.no_extras:
         out["bkw_maxwell"] = bench_bkw(fks, torch, dev)
+        progress("bkw done")
         out["uneven_batch"] = bench_uneven(fks, torch, dev)
+        progress("uneven batch done")
         out["fks_step_box"] = bench_fks_step(fks, torch, dev)
+        progress("box steps done")
         out["surrogate"] = bench_surrogate(fks, torch, dev, train_seconds=args.sur_train_seconds,
                                            pairs=args.sur_pairs)
     if cpu is not None:

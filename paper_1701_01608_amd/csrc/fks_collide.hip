@@ -72,6 +72,8 @@ struct Cfg : Grid<T, N> {
   static constexpr int Z = P / S;
   static constexpr int LINES = Z * P;  // x lines (z', y) of the slab
   static constexpr int NCH = (N + Z - 1) / Z;  // k_z chunks of the fold period Z
+  // half chunks of stage-1 loads in flight per thread (FP32: four, i.e. two chunks)
+  static constexpr int DEPTH = GREG ? 4 : 2;
   static constexpr int NT = GREG ? ((2 * LINES + 63) / 64) * 64 : 256;
   static constexpr size_t w_elems = size_t(Z) * K * WS;
   static constexpr size_t w_bytes = w_elems * sizeof(cpx<T>);
@@ -284,34 +286,32 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   // once after the last chunk.  Output: the Z planes [z'][kx + Kh][ky + Kh] of dst with
   // row stride `ld`.
   //
-  // The rows are streamed through a two-deep software pipeline of half chunks: the loads
-  // of the next half chunk are in flight while the current one is accumulated.  The
-  // pipeline is primed (stage1_issue: both halves of chunk 0) before `mid` runs and
+  // The rows are streamed through a software pipeline of DEPTH half chunks: the loads of
+  // the next half chunks are in flight while the current one is accumulated.  The
+  // pipeline is primed (stage1_issue: the first DEPTH half chunks) before `mid` runs and
   // drained after it (stage1_finish), so that independent work placed in `mid` hides the
   // latency of the first loads.
   constexpr int ZH = (Z + 1) / 2;
-  using H0 = std::integral_constant<int, 0>;
-  using H1 = std::integral_constant<int, 1>;
+  // DEPTH half-chunk slots in flight (a ring over the 2*NCH half chunks)
+  constexpr int DEPTH = C::DEPTH < 2 * C::NCH ? C::DEPTH : 2 * C::NCH;
   struct Pipe {
-    cpx<T> pf0[ZH], pa0[ZH], pf1[ZH], pa1[ZH];
+    cpx<T> pf[DEPTH][ZH], pa[DEPTH][ZH];
   };
-  auto load_half = [&](cpx<T>* pf, cpx<T>* pa, uint32_t voff, uint32_t tterm, auto jc, auto half) {
-    constexpr int b0 = decltype(half)::value * ZH;
-    constexpr uint32_t s0 = uint32_t(decltype(jc)::value) * Z * row_bytes;
+  auto load_half = [&](Pipe& q, uint32_t voff, uint32_t tterm, auto hc) {
+    constexpr int h = decltype(hc)::value, slot = h % DEPTH, b0 = (h % 2) * ZH;
+    constexpr uint32_t s0 = uint32_t(h / 2) * Z * row_bytes;
     static_for<0, ZH>([&](auto i) {
       constexpr int bb = b0 + decltype(i)::value;
       if constexpr (bb < Z) {
-        pf[i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
-        pa[i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
+        q.pf[slot][i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
+        q.pa[slot][i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
       }
     });
   };
   auto stage1_issue = [&](Pipe& q, int p, int t) {
     const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
     const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
-    using J0 = std::integral_constant<int, 0>;
-    load_half(q.pf0, q.pa0, voff, tterm, J0{}, H0{});
-    load_half(q.pf1, q.pa1, voff, tterm, J0{}, H1{});
+    static_for<0, DEPTH>([&](auto hc) { load_half(q, voff, tterm, hc); });
   };
   auto stage1_finish = [&](Pipe& q, int p, int t, cpx<T>* dst, auto ld_c) {
     constexpr int LD = decltype(ld_c)::value;
@@ -330,14 +330,14 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
       s3[bb] = T(0);
       s4[bb] = T(0);
     });
-    auto accumulate = [&](const cpx<T>* pf, const cpx<T>* pa, auto jc, auto half) {
-      constexpr int b0 = decltype(half)::value * ZH;
-      constexpr long qe = long(decltype(jc)::value) * RID;
+    auto accumulate = [&](auto hc) {
+      constexpr int h = decltype(hc)::value, slot = h % DEPTH, b0 = (h % 2) * ZH;
+      constexpr long qe = long(h / 2) * RID;
       static_for<0, ZH>([&](auto i) {
         constexpr int bb = b0 + decltype(i)::value;
         if constexpr (bb < Z) {
-          const cpx<T> ab = pa[i];
-          const cpx<T> g = twiddle<C::S, +1, qe>(pf[i]);
+          const cpx<T> ab = q.pa[slot][i];
+          const cpx<T> g = twiddle<C::S, +1, qe>(q.pf[slot][i]);
           s1[bb] += ab.re * g.re;
           s2[bb] += ab.im * g.im;
           s3[bb] += ab.re * g.im;
@@ -345,16 +345,12 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
         }
       });
     };
-    static_for<0, C::NCH>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      using JN = std::integral_constant<int, (j + 1 < C::NCH ? j + 1 : j)>;
-      // no load is hoisted past its half chunk (keeps the pipeline two deep)
+    static_for<0, 2 * C::NCH>([&](auto hc) {
+      constexpr int h = decltype(hc)::value;
+      // no load is hoisted past the half chunk that frees its slot
       sched_fence();
-      accumulate(q.pf0, q.pa0, jc, H0{});
-      if constexpr (j + 1 < C::NCH) load_half(q.pf0, q.pa0, voff, tterm, JN{}, H0{});
-      sched_fence();
-      accumulate(q.pf1, q.pa1, jc, H1{});
-      if constexpr (j + 1 < C::NCH) load_half(q.pf1, q.pa1, voff, tterm, JN{}, H1{});
+      accumulate(hc);
+      if constexpr (h + DEPTH < 2 * C::NCH) load_half(q, voff, tterm, std::integral_constant<int, h + DEPTH>{});
     });
     // per-bin twiddles and the bin of each partial sum (k_z mod Z, resp. -k_z mod Z)
     cpx<T> oA[Z], oB[Z];
