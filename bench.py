@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "0a83d09e20118c4d", "bytes": 2326638985}
+SLAB_TRAFFIC = {"sha": "57f64b4489e6a198", "bytes": 2334119812}
 
 
 def progress(msg):

@@ -80,7 +80,11 @@ struct Cfg : Grid<T, N> {
   // FP32: stage 1's output buffer [Z][K][K] beside W (double buffering across terms)
   static constexpr size_t x_bytes = GREG ? size_t(Z) * K * K * sizeof(cpx<T>) : 0;
   // after the last term: G staged as [LINES][P] reals, then its x spectra [Z][KH1][WS]
-  static constexpr size_t gst_bytes = GREG ? ((size_t(LINES) * P * sizeof(T) + 255) / 256) * 256 : 0;
+  // row stride of the staged G lines: P + 2 floats keeps the rows 8-byte aligned and
+  // spreads the lanes of a wave (one line each) over the LDS banks; with stride P = 48 a
+  // wave's 64 lanes fall into 4 banks
+  static constexpr int GS = P + 2;
+  static constexpr size_t gst_bytes = GREG ? ((size_t(LINES) * GS * sizeof(T) + 255) / 256) * 256 : 0;
   static constexpr size_t spec_bytes = size_t(Z) * KH1 * WS * sizeof(cpx<T>);
   static constexpr size_t lds_bytes =
       (w_bytes + x_bytes > gst_bytes + spec_bytes) ? w_bytes + x_bytes : gst_bytes + spec_bytes;
@@ -488,13 +492,13 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     Wspec = reinterpret_cast<cpx<T>*>(reinterpret_cast<unsigned char*>(W) + C::gst_bytes);
     if (tid < 2 * C::LINES) {
       const int h = tid / C::LINES, line = tid - h * C::LINES;
-      static_for<0, P / 2>([&](auto j) { Gst[size_t(line) * P + 2 * decltype(j)::value + h] = g[j]; });
+      static_for<0, P / 2>([&](auto j) { Gst[size_t(line) * C::GS + 2 * decltype(j)::value + h] = g[j]; });
     }
     __syncthreads();
     for (int it = tid; it < C::LINES; it += NT) {
       const int zp = it / P, y = it % P;
       cpx<T> o[KH1];
-      rdft_low<P, KH1>(Gst + size_t(it) * P, o);
+      rdft_low<P, KH1>(Gst + size_t(it) * C::GS, o);
       static_for<0, KH1>([&](auto kx) { Wspec[(size_t(zp) * KH1 + kx) * WS + y] = o[kx]; });
     }
   } else {
