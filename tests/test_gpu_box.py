@@ -58,3 +58,54 @@ def test_full_box_step_sampled_parity():
         assert err <= 1e-6, (i, j, k, err)
     # transport permutes, the collision conserves mass per cell to FP32 rounding
     assert abs(mass1 - mass0) <= 1e-6 * mass0
+
+
+# The paper's own Boltzmann mesh (§5, 3D Sod explosion): 64^3 cells x 16^3 velocities on
+# the velocity box [-15, 15)^3, ball |x - (1,1,1)| < 0.2 at rho = 1, T = 5, elsewhere
+# rho = 0.125, T = 4, u = 0; 33 steps to t = 0.07.  Carleman radius R = 0.75 L (the ratio
+# of the n = 32 workloads, inside the no-overlap bound 4L/(3+sqrt 2)).
+SOD_N, SOD_L = 16, 15.0
+SOD_R = 0.75 * SOD_L
+SOD_SHAPE = (64, 64, 64)
+SOD_DX = 2.0 / 64
+SOD_DT = 0.07 / 33
+
+
+def sod_box_device():
+    m_in, m_out = fks_inputs.maxwellian_on_grid(SOD_N, SOD_L, [1.0, 0.125], [[0.0] * 3, [0.0] * 3], [5.0, 4.0])
+    xs = (np.arange(SOD_SHAPE[0]) + 0.5) * SOD_DX
+    X, Y, Z = np.meshgrid(xs, xs, xs, indexing="ij")
+    inside = (((X - 1) ** 2 + (Y - 1) ** 2 + (Z - 1) ** 2) < 0.04).reshape(-1)
+    mi = torch.tensor(m_in, dtype=torch.float32, device="cuda").reshape(1, -1)
+    mo = torch.tensor(m_out, dtype=torch.float32, device="cuda").reshape(1, -1)
+    ins = torch.tensor(inside, device="cuda").reshape(-1, 1)
+    f = torch.where(ins, mi, mo).reshape(-1, SOD_N, SOD_N, SOD_N).contiguous()
+    return f, m_in, m_out, inside.reshape(SOD_SHAPE)
+
+
+def test_sod_mesh_step_sampled_parity():
+    from paper_1701_01608_amd import Plan, Transport, step
+    f, m_in, m_out, inside = sod_box_device()
+    mass0 = float(f.double().sum())
+    plan = Plan(SOD_N, SOD_L, SOD_R, dtype="f32", max_cells=4096)
+    xp = Transport(SOD_N, SOD_L, SOD_SHAPE, SOD_DX)
+    step(plan, xp, f, SOD_DT, n_steps=1)
+    torch.cuda.synchronize()
+    mass1 = float(f.double().sum())
+    vel = otr.velocity_table(SOD_N, SOD_L)
+    delta, _ = otr.advance(np.zeros_like(vel), vel, SOD_DT, SOD_DX)
+    assert np.abs(delta).max() >= 1     # the fastest particles change cell in this step
+    op = oracle_plan(SOD_N, SOD_L, SOD_R)
+    mi32, mo32 = m_in.astype(np.float32).reshape(-1), m_out.astype(np.float32).reshape(-1)
+    # ball centre, ball edge (cells whose velocities come from both states), far corner
+    cells = [(31, 31, 31), (32, 25, 32), (38, 32, 32), (0, 63, 5)]
+    for (i, j, k) in cells:
+        si = (i - delta[:, 0]) % SOD_SHAPE[0]
+        sj = (j - delta[:, 1]) % SOD_SHAPE[1]
+        sk = (k - delta[:, 2]) % SOD_SHAPE[2]
+        fstar = np.where(inside[si, sj, sk], mi32, mo32).astype(np.float64).reshape(SOD_N, SOD_N, SOD_N)
+        ref = fstar + SOD_DT * collide_fast(fstar, op)
+        got = f[(i * SOD_SHAPE[1] + j) * SOD_SHAPE[2] + k].double().cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-6, (i, j, k, err)
+    assert abs(mass1 - mass0) <= 1e-6 * mass0
