@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "57f64b4489e6a198", "bytes": 2334119812}
+SLAB_TRAFFIC = {"sha": "8eba53d85d8bd7ca", "bytes": 2334277884}
 
 
 def progress(msg):
@@ -311,32 +311,36 @@ def bench_fks_step(fks, torch, dev, steps=20):
             "box_mass_rel_change": abs(mass - mass0) / mass0}
 
 
-def bench_sod(fks, torch, dev, dtype="f32", steps=33):
-    """The paper's own Boltzmann mesh on one GPU: 3D Sod explosion, 64^3 cells x 16^3
-    velocities on [-15, 15)^3 (1.07 GB in FP32), hard spheres M = 16 (4 x 4), R = 11.25,
-    P = 24; ball |x - (1,1,1)| < 0.2 at rho = 1, T = 5, elsewhere rho = 0.125, T = 4,
-    u = 0; steps of exact transport + Euler collision with dt = 0.07/33 (33 steps reach
-    t = 0.07)."""
+def bench_sod(fks, torch, dev, dtype="f32", steps=33, n=16):
+    """The paper's own Boltzmann meshes on one GPU: 3D Sod explosion, 64^3 cells x n^3
+    velocities on [-15, 15)^3 (n = 16: 1.07 GB, n = 32: 34 GB in FP32), hard
+    spheres M = 16 (4 x 4), R = 11.25, P = 3n/2; ball |x - (1,1,1)| < 0.2 at rho = 1,
+    T = 5, elsewhere rho = 0.125, T = 4, u = 0; steps of exact transport + Euler collision
+    with dt = 0.07/33 (33 steps reach t = 0.07)."""
     import fks_inputs
-    n, Lv, shape = 16, 15.0, (64, 64, 64)
+    Lv, shape = 15.0, (64, 64, 64)
     dx, dt = 2.0 / 64, 0.07 / 33
     tdt = torch.float32 if dtype == "f32" else torch.float64
     m_in, m_out = fks_inputs.maxwellian_on_grid(n, Lv, [1.0, 0.125], [[0.0] * 3, [0.0] * 3], [5.0, 4.0])
     xs = (np.arange(64) + 0.5) * dx
     X, Y, Z = np.meshgrid(xs, xs, xs, indexing="ij")
     inside = torch.tensor((((X - 1) ** 2 + (Y - 1) ** 2 + (Z - 1) ** 2) < 0.04).reshape(-1, 1), device=dev)
-    f = torch.where(inside, torch.tensor(m_in, dtype=tdt, device=dev).reshape(1, -1),
-                    torch.tensor(m_out, dtype=tdt, device=dev).reshape(1, -1))
-    f = f.reshape(-1, n, n, n).contiguous()
-    f0 = f.clone()
+    mi = torch.tensor(m_in, dtype=tdt, device=dev).reshape(1, -1)
+    mo = torch.tensor(m_out, dtype=tdt, device=dev).reshape(1, -1)
+
+    def initial_state():
+        return torch.where(inside, mi, mo).reshape(-1, n, n, n)
+
+    f = initial_state()
     cells = f.shape[0]
     plan = fks.Plan(n, Lv, 0.75 * Lv, a1=4, a2=4, C=0.25, dtype=dtype, max_cells=CELLS)
     xp = fks.Transport(n, Lv, shape, dx)
     tmp = torch.empty_like(f)
     mom = torch.empty((cells, 5), dtype=torch.float64, device=dev)
-    mass0 = float(f.double().sum())
+    mass0 = float(f.sum(dtype=torch.float64))
     fks.step(plan, xp, f, dt, n_steps=1, f_tmp=tmp)      # warm-up step (then restart)
-    f.copy_(f0)
+    del f
+    f = initial_state()
     xp = fks.Transport(n, Lv, shape, dx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -345,7 +349,7 @@ def bench_sod(fks, torch, dev, dtype="f32", steps=33):
     wall = time.perf_counter() - t0
     mass = float(mom[:, 0].sum()) / (2.0 * Lv / n) ** 3
     rho = mom[:, 0].reshape(shape)                         # dv^3 sum f: the density
-    return {"workload": f"3D Sod explosion on the paper's 64^3 x 16^3 Boltzmann mesh, velocity box [-15,15)^3, "
+    return {"workload": f"3D Sod explosion on the paper's 64^3 x {n}^3 Boltzmann mesh, velocity box [-15,15)^3, "
                         f"{dtype.upper()}, hard spheres M=16, transport + Euler collision, dt=0.07/33",
             "steps": steps, "t_end": round(steps * dt, 5), "ms_per_step": round(wall * 1e3 / steps, 3),
             "value": round(cells * n ** 3 * steps / wall, 1), "unit": "cells*N^3/s",
@@ -396,7 +400,8 @@ def main():
         import paper_1701_01608_amd as fks
         dev = torch.device("cuda:0")
         print(json.dumps({"sod_paper_mesh": {"f32": bench_sod(fks, torch, dev),
-                                             "f64": bench_sod(fks, torch, dev, dtype="f64", steps=8)}}),
+                                             "f64": bench_sod(fks, torch, dev, dtype="f64", steps=8),
+                                             "n32_f32": bench_sod(fks, torch, dev, steps=4, n=32)}}),
               flush=True)
         return
     if args.only_surrogate:
@@ -498,6 +503,8 @@ def main():
         progress("sod mesh (FP32) done")
         out["sod_paper_mesh"]["f64"] = bench_sod(fks, torch, dev, dtype="f64", steps=8)
         progress("sod mesh (FP64) done")
+        out["sod_paper_mesh"]["n32_f32"] = bench_sod(fks, torch, dev, steps=4, n=32)
+        progress("sod mesh 64^3 x 32^3 done")
         out["surrogate"] = bench_surrogate(fks, torch, dev, train_seconds=args.sur_train_seconds,
                                            pairs=args.sur_pairs)
     if cpu is not None:

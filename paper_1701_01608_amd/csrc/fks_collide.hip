@@ -857,12 +857,15 @@ __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ f, double
 // Heun combination f = (f + g)/2
 template <typename T>
 __global__ __launch_bounds__(256) void k_average(T* __restrict__ f, const T* __restrict__ g, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) f[i] = T(0.5) * (f[i] + g[i]);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    f[i] = T(0.5) * (f[i] + g[i]);
 }
 
 hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, void* stream) {
-  const dim3 grid(unsigned((n + 255) / 256));
+  // at most 2^22 blocks; the threads stride over the rest
+  const int64_t blocks = (n + 255) / 256;
+  const dim3 grid(unsigned(blocks < (int64_t(1) << 22) ? (blocks > 0 ? blocks : 1) : (int64_t(1) << 22)));
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype_is_f32)
     hipLaunchKernelGGL(k_average<float>, grid, dim3(256), 0, st, static_cast<float*>(f),

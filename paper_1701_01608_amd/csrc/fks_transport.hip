@@ -40,23 +40,29 @@ __global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int n, doubl
 }
 
 // f_out[cell][k] = f_in[(cell - delta_k) mod box][k]; one thread per (cell, velocity),
-// consecutive threads on consecutive velocities of one destination cell.
+// consecutive threads on consecutive velocities of one destination cell.  The grid holds
+// blocks_per_cell blocks for each of a bounded number of cells and strides over the rest
+// (the threads of one launch stay below 2^32 for any box).
 template <typename T>
 __global__ __launch_bounds__(256) void k_roll(const T* __restrict__ fin, T* __restrict__ fout,
                                               const int32_t* __restrict__ dl, int nv, int nx, int ny, int nz,
                                               int blocks_per_cell) {
-  const int cell = blockIdx.x / blocks_per_cell;
   const int k = (blockIdx.x % blocks_per_cell) * blockDim.x + threadIdx.x;
   if (k >= nv) return;
-  const int cx = cell / (ny * nz), cy = (cell / nz) % ny, cz = cell % nz;
-  int sx = (cx - dl[3 * k + 0]) % nx;
-  int sy = (cy - dl[3 * k + 1]) % ny;
-  int sz = (cz - dl[3 * k + 2]) % nz;
-  sx += (sx < 0) ? nx : 0;
-  sy += (sy < 0) ? ny : 0;
-  sz += (sz < 0) ? nz : 0;
-  const size_t src = (size_t(sx) * ny + sy) * nz + sz;
-  fout[size_t(cell) * nv + k] = fin[src * nv + k];
+  const int dx = dl[3 * k + 0], dy = dl[3 * k + 1], dz = dl[3 * k + 2];
+  const int64_t cells = int64_t(nx) * ny * nz;
+  const int64_t stride = gridDim.x / blocks_per_cell;
+  for (int64_t cell = blockIdx.x / blocks_per_cell; cell < cells; cell += stride) {
+    const int cx = int(cell / (int64_t(ny) * nz)), cy = int((cell / nz) % ny), cz = int(cell % nz);
+    int sx = (cx - dx) % nx;
+    int sy = (cy - dy) % ny;
+    int sz = (cz - dz) % nz;
+    sx += (sx < 0) ? nx : 0;
+    sy += (sy < 0) ? ny : 0;
+    sz += (sz < 0) ? nz : 0;
+    const size_t src = (size_t(sx) * ny + sy) * nz + sz;
+    fout[size_t(cell) * nv + k] = fin[src * nv + k];
+  }
 }
 
 hipError_t launch_xport_reset(const XportState& st, int nv, void* stream) {
@@ -79,7 +85,9 @@ hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int3
                        int nz, void* stream) {
   const int bpc = (nv + 255) / 256;
   const long cells = long(nx) * ny * nz;
-  const dim3 grid(unsigned(cells * bpc));
+  // at most 2^22 blocks (2^30 threads); each block strides over its cells
+  const long max_cells = (1L << 22) / bpc > 0 ? (1L << 22) / bpc : 1;
+  const dim3 grid(unsigned((cells < max_cells ? cells : max_cells) * bpc));
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_mark(kProfRoll, true, st);
   if (dtype_is_f32)

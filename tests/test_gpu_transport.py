@@ -64,3 +64,27 @@ def test_fks_step_small_box(dtype):
     tol = 1e-5 if dtype == "f32" else 1e-11
     assert np.linalg.norm(out - g) / np.linalg.norm(g) <= tol
     np.testing.assert_allclose(mom.cpu().numpy(), oracle_moments(out, op.grid), rtol=1e-12, atol=1e-14)
+
+
+def test_roll_beyond_2_pow_32_elements():
+    # 64 x 64 x 33 cells x 32^3 velocities = 4.43e9 values (17.7 GB per FP32 buffer): one
+    # launch of one thread per value would exceed the 2^32 threads of a grid, so the roll
+    # strides over cells.  Each cell holds its own index (exact in FP32 below 2^24); after
+    # one step every sampled cell must hold, per velocity, the index of its source cell.
+    from paper_1701_01608_amd import Transport
+    n, L, shape, dx, dt = 32, 15.0, (64, 64, 33), 2.0 / 64, 0.07 / 33
+    cells, nv = int(np.prod(shape)), n ** 3
+    assert cells * nv > 2 ** 32
+    f = torch.arange(cells, dtype=torch.float32, device="cuda").reshape(-1, 1).expand(cells, nv).contiguous()
+    xp = Transport(n, L, shape, dx)
+    out = xp(f.view(cells, n, n, n), dt=dt)
+    torch.cuda.synchronize()
+    del f
+    vel = otr.velocity_table(n, L)
+    d, _ = otr.advance(np.zeros_like(vel), vel, dt, dx)
+    assert np.abs(d).max() >= 1
+    for c in (0, 1, cells // 2 + 7, cells - 1):
+        cx, cy, cz = c // (shape[1] * shape[2]), (c // shape[2]) % shape[1], c % shape[2]
+        src = (((cx - d[:, 0]) % shape[0]) * shape[1] + (cy - d[:, 1]) % shape[1]) * shape[2] + (cz - d[:, 2]) % shape[2]
+        got = out[c].reshape(-1).cpu().numpy()
+        assert np.array_equal(got, src.astype(np.float32)), c
