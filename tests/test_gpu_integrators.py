@@ -90,3 +90,24 @@ def test_graph_of_split_steps():
         step(plan, xa, eager, dt, n_steps=1)
         torch.cuda.synchronize()
         assert torch.equal(fg, eager), f"replay {rep}"
+
+
+def test_heun_on_a_batch_beyond_the_bounded_grid():
+    # 40960 cells at n = 32 (1.34e9 values): the averaging kernel's grid covers 2^30
+    # values and strides over the rest, so the cells past 32768 take the stride path.
+    # Four hard-sphere mixtures repeated; sampled cells on both sides against the oracle.
+    from paper_1701_01608_amd import Plan
+    n, Lh, Rh, dt, reps = 32, 8.0, 6.0, 0.01, 10240
+    base = fks_inputs.maxwellian_mixture(n, Lh, 4, seed=11).astype(np.float32)
+    f = torch.tensor(base, device="cuda").repeat(reps, 1, 1, 1)
+    assert f.numel() > 2 ** 30
+    plan = Plan(n, Lh, Rh, a1=4, a2=4, C=0.25, dtype="f32", max_cells=4096)
+    plan.heun(f, dt, n_steps=1)
+    torch.cuda.synchronize()
+    op = oracle_plan(n, Lh, Rh, a1=4, a2=4, C=0.25)
+    cells = f.shape[0]
+    for c in (5, cells - 1):
+        ref = oracle_heun(base[c % 4].astype(np.float64), lambda x: collide_fast(x, op), dt)
+        got = f[c].double().cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-6, (c, err)
