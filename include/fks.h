@@ -88,7 +88,9 @@ typedef struct fks_xport_s* fks_xport;
 /* ---- collision operator --------------------------------------------------------- */
 
 /* Builds the FP64 kernel tables on the host (Appendix A: phi_R, psi_R, directions,
- * radial nodes, loss weight) for batches of up to max_cells cells (>= 1).  Host only. */
+ * radial nodes, loss weight) for batches of up to max_cells cells (1 .. 2^19, so that
+ * one chunk's launches stay within the 2^32 threads of a grid; larger batches are
+ * processed in chunks of max_cells).  FKS_E_ARG outside that range.  Host only. */
 fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_plan* out);
 
 /* Bytes of the device table buffer and of the device workspace (for max_cells cells). */

@@ -448,6 +448,8 @@ fks_status fks_profile_stop(fks_profile_stats* out) {
 }
 const char* fks_version(void) { return "fks 0.1 (gfx950)"; }
 
+constexpr int64_t kMaxChunkCells = int64_t(1) << 19;
+
 fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_plan* out) {
   if (!desc || !out) return fail(FKS_E_ARG, "null argument");
   *out = nullptr;
@@ -468,7 +470,10 @@ fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_
   }
   if (d.dtype != FKS_F32 && d.dtype != FKS_F64) return fail(FKS_E_ARG, "dtype must be FKS_F32 or FKS_F64");
   if (d.flags & ~(FKS_CONSERVE | FKS_ALLOW_OVERLAP)) return fail(FKS_E_ARG, "unknown flags 0x%x", d.flags);
-  if (max_cells < 1 || max_cells > (int64_t(1) << 26)) return fail(FKS_E_ARG, "max_cells out of range");
+  // one chunk's slab launch (cells x slabs x threads per slab, at most 4608 threads per
+  // cell) stays below the 2^32 threads of a grid
+  if (max_cells < 1 || max_cells > kMaxChunkCells)
+    return fail(FKS_E_ARG, "max_cells out of range (1 .. %lld)", (long long)kMaxChunkCells);
   const int nr = d.kernel == FKS_VHS ? d.n_radial : 1;
   if (int64_t(d.a1) * d.a2 * nr > 8192) return fail(FKS_E_ARG, "too many separable terms");
 

@@ -75,6 +75,17 @@ def test_plan_create_rejects(lib, bad, status):
     assert lib.lib().fks_last_error()
 
 
+def test_max_cells_limit(lib):
+    # one chunk's launches stay within the 2^32 threads of a grid: max_cells <= 2^19
+    for m, ok in ((1 << 19, True), ((1 << 19) + 1, False), (0, False)):
+        st, h = _create(lib, _desc(lib), max_cells=m)
+        assert (st == 0) == ok, (m, st)
+        if ok:
+            lib.lib().fks_plan_destroy(h)
+        else:
+            assert st == -1 and b"max_cells" in lib.lib().fks_last_error()
+
+
 def test_overlap_flag_allows_large_R(lib):
     st, h = _create(lib, _desc(lib, R=7.5, flags=lib.FKS_ALLOW_OVERLAP))
     assert st == 0
