@@ -313,7 +313,7 @@ def bench_fks_step(fks, torch, dev, steps=20):
 
 def bench_sod(fks, torch, dev, dtype="f32", steps=33, n=16):
     """The paper's own Boltzmann meshes on one GPU: 3D Sod explosion, 64^3 cells x n^3
-    velocities on [-15, 15)^3 (n = 16: 1.07 GB, n = 32: 34 GB in FP32), hard
+    velocities on [-15, 15)^3 (n = 16: 1.07 GB, n = 32: 34 GB in FP32, 69 GB in FP64), hard
     spheres M = 16 (4 x 4), R = 11.25, P = 3n/2; ball |x - (1,1,1)| < 0.2 at rho = 1,
     T = 5, elsewhere rho = 0.125, T = 4, u = 0; steps of exact transport + Euler collision
     with dt = 0.07/33 (33 steps reach t = 0.07)."""
@@ -401,7 +401,8 @@ def main():
         dev = torch.device("cuda:0")
         print(json.dumps({"sod_paper_mesh": {"f32": bench_sod(fks, torch, dev),
                                              "f64": bench_sod(fks, torch, dev, dtype="f64", steps=8),
-                                             "n32_f32": bench_sod(fks, torch, dev, steps=4, n=32)}}),
+                                             "n32_f32": bench_sod(fks, torch, dev, steps=4, n=32),
+                                             "n32_f64": bench_sod(fks, torch, dev, dtype="f64", steps=2, n=32)}}),
               flush=True)
         return
     if args.only_surrogate:
@@ -504,7 +505,9 @@ def main():
         out["sod_paper_mesh"]["f64"] = bench_sod(fks, torch, dev, dtype="f64", steps=8)
         progress("sod mesh (FP64) done")
         out["sod_paper_mesh"]["n32_f32"] = bench_sod(fks, torch, dev, steps=4, n=32)
-        progress("sod mesh 64^3 x 32^3 done")
+        progress("sod mesh 64^3 x 32^3 (FP32) done")
+        out["sod_paper_mesh"]["n32_f64"] = bench_sod(fks, torch, dev, dtype="f64", steps=2, n=32)
+        progress("sod mesh 64^3 x 32^3 (FP64) done")
         out["surrogate"] = bench_surrogate(fks, torch, dev, train_seconds=args.sur_train_seconds,
                                            pairs=args.sur_pairs)
     if cpu is not None:
