@@ -349,12 +349,15 @@ def bench_sod(fks, torch, dev, dtype="f32", steps=33, n=16):
     wall = time.perf_counter() - t0
     mass = float(mom[:, 0].sum()) / (2.0 * Lv / n) ** 3
     rho = mom[:, 0].reshape(shape)                         # dv^3 sum f: the density
-    return {"workload": f"3D Sod explosion on the paper's 64^3 x {n}^3 Boltzmann mesh, velocity box [-15,15)^3, "
+    out = {"workload": f"3D Sod explosion on the paper's 64^3 x {n}^3 Boltzmann mesh, velocity box [-15,15)^3, "
                         f"{dtype.upper()}, hard spheres M=16, transport + Euler collision, dt=0.07/33",
             "steps": steps, "t_end": round(steps * dt, 5), "ms_per_step": round(wall * 1e3 / steps, 3),
             "value": round(cells * n ** 3 * steps / wall, 1), "unit": "cells*N^3/s",
             "box_mass_rel_change": abs(mass - mass0) / mass0,
             "density_range": [float(rho.min()), float(rho.max())]}
+    del f, tmp, mom, rho, plan, xp
+    torch.cuda.empty_cache()                               # the next workload's buffers differ in size
+    return out
 
 
 def main():
