@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "8eba53d85d8bd7ca", "bytes": 2334277884}
+SLAB_TRAFFIC = {"sha": "b0a1431043e711e4", "bytes": 2304626691}
 
 
 def progress(msg):
@@ -44,9 +44,15 @@ def progress(msg):
 
 
 def kernel_sources_hash():
+    """Hash of the collision kernels' sources and of the flags they are compiled with."""
     import hashlib
-    d = os.path.join(ROOT, "paper_1701_01608_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_1701_01608_amd")
+    d = os.path.join(pkg, "csrc")
     src = open(os.path.join(d, "fks_collide.hip"), "rb").read() + open(os.path.join(d, "fks_fft.hpp"), "rb").read()
+    sys.path.insert(0, ROOT)
+    from paper_1701_01608_amd import build
+    flags = [a for a in build.COMMON + build.FFT_FLAGS if os.sep not in a]   # no machine paths
+    src += " ".join(flags).encode()
     return hashlib.sha256(src).hexdigest()[:16]
 
 
