@@ -1,0 +1,65 @@
+"""Macroscopic variables and the BGK relaxation operator (FP64).
+
+Test infrastructure only (see the package header).
+
+Section 2 of the paper: the conservative variables are U = (rho, rho u, E), the
+moments of f against phi(v) = (1, v, |v|^2/2); the temperature follows from
+(3/2) rho T = E - (1/2) rho |u|^2; the local equilibrium is the Maxwellian
+M[f](v) = rho (2 pi T)^{-3/2} exp(-|v - u|^2 / (2T)); the BGK operator is
+Q_BGK(f) = nu (M[f] - f) with the collision frequency nu.
+
+Section 2.2.1: in the FKS the BGK collision term of velocity v_k in cell j is
+nu (E_jk - f_jk), E_jk the Maxwellian of the cell's macroscopic variables
+evaluated at v_k.  The macroscopic variables are collision invariants, so they
+do not change during the relaxation and E is fixed over the collision step.
+
+Relaxation of one step dt at frozen E (the collision stage of eq. disc_relax):
+  euler: f + dt nu (E - f)             (eq. disc_relax)
+  exact: E + (f - E) exp(-nu dt)        (the ODE df/dt = nu (E - f) solved exactly;
+                                         stable and positivity preserving for any
+                                         nu dt, the stiff limit named in Section 2.1)
+"""
+
+import numpy as np
+
+from .grid import Grid, velocity_vectors
+
+
+def primitive(U):
+    """ToPrimitive: U (..., 5) = (rho, rho u_x, rho u_y, rho u_z, E) -> (rho, u_x, u_y, u_z, T)."""
+    U = np.asarray(U, dtype=np.float64)
+    rho = U[..., 0]
+    u = U[..., 1:4] / rho[..., None]
+    T = (2.0 / 3.0) * (U[..., 4] / rho - 0.5 * np.sum(u * u, axis=-1))
+    return np.concatenate([rho[..., None], u, T[..., None]], axis=-1)
+
+
+def conservative(W):
+    """ToConservative: (rho, u, T) -> (rho, rho u, E) with E = (3/2) rho T + (1/2) rho |u|^2."""
+    W = np.asarray(W, dtype=np.float64)
+    rho = W[..., 0]
+    u = W[..., 1:4]
+    T = W[..., 4]
+    E = 1.5 * rho * T + 0.5 * rho * np.sum(u * u, axis=-1)
+    return np.concatenate([rho[..., None], rho[..., None] * u, E[..., None]], axis=-1)
+
+
+def maxwellian(W, g: Grid):
+    """M(v_k) = rho (2 pi T)^{-3/2} exp(-|v_k - u|^2 / (2T)) on the grid, for one cell W (5,)."""
+    rho, u, T = W[0], np.asarray(W[1:4]), W[4]
+    V = velocity_vectors(g)
+    w2 = np.sum((V - u) ** 2, axis=-1)
+    return rho * (2.0 * np.pi * T) ** -1.5 * np.exp(-w2 / (2.0 * T))
+
+
+def bgk_operator(f, W, nu, g: Grid):
+    """Q_BGK = nu (M[W] - f) for one cell."""
+    return nu * (maxwellian(W, g) - f)
+
+
+def relax_euler(f, E, nu, dt):
+    return f + dt * nu * (E - f)
+
+
+def relax_exact(f, E, nu, dt):
+    return E + (f - E) * np.exp(-nu * dt)
