@@ -13,6 +13,14 @@ nu (E_jk - f_jk), E_jk the Maxwellian of the cell's macroscopic variables
 evaluated at v_k.  The macroscopic variables are collision invariants, so they
 do not change during the relaxation and E is fixed over the collision step.
 
+The sampled Maxwellian M[W](v_k) does not have exactly the discrete moments U on the
+truncated grid (the tails beyond the box and the rectangle rule), so a relaxation
+towards it would change U, which the FKS keeps by eq. DM_update assuming collisions
+conserve.  The "suitable approximation" E used here is the sampled Maxwellian times
+the affine correction in the invariants that restores the moments exactly:
+    E = M (1 + lambda . phi),  G lambda = U - dv^3 sum_k M phi,  G = dv^3 sum_k M phi phi^T.
+For a well-resolved Maxwellian lambda is at rounding level and E = M.
+
 Relaxation of one step dt at frozen E (the collision stage of eq. disc_relax):
   euler: f + dt nu (E - f)             (eq. disc_relax)
   exact: E + (f - E) exp(-nu dt)        (the ODE df/dt = nu (E - f) solved exactly;
@@ -52,9 +60,22 @@ def maxwellian(W, g: Grid):
     return rho * (2.0 * np.pi * T) ** -1.5 * np.exp(-w2 / (2.0 * T))
 
 
-def bgk_operator(f, W, nu, g: Grid):
-    """Q_BGK = nu (M[W] - f) for one cell."""
-    return nu * (maxwellian(W, g) - f)
+def conservative_maxwellian(U, g: Grid):
+    """E = M (1 + lambda . phi) with the discrete moments of E equal to U (one cell, U (5,))."""
+    U = np.asarray(U, dtype=np.float64)
+    M = maxwellian(primitive(U), g).reshape(-1)
+    V = velocity_vectors(g).reshape(-1, 3)
+    phi = np.stack([np.ones(len(V)), V[:, 0], V[:, 1], V[:, 2], 0.5 * np.sum(V * V, axis=1)])
+    w = g.dv ** 3
+    G = (phi * M) @ phi.T * w
+    m = phi @ M * w
+    lam = np.linalg.solve(G, U - m)
+    return (M * (1.0 + lam @ phi)).reshape(g.n, g.n, g.n)
+
+
+def bgk_operator(f, U, nu, g: Grid):
+    """Q_BGK = nu (E[U] - f) for one cell with conservative variables U."""
+    return nu * (conservative_maxwellian(U, g) - f)
 
 
 def relax_euler(f, E, nu, dt):

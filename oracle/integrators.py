@@ -21,7 +21,7 @@ fks_step: one split step of Section 2.1 on a periodic box of cells: exact
        every cell.
 fks_step_bgk: the sequential FKS algorithm of Section 4.1 with the BGK operator:
        transport, conservative variables by eq. DM_update, relaxation towards the
-       cells' Maxwellians (Section 2.2.1).
+       cells' moment-preserving Maxwellians (Section 2.2.1; bgk.conservative_maxwellian).
 """
 
 import numpy as np
@@ -73,10 +73,9 @@ def fks_step_bgk(f_cells, U, s, grid, shape, dx, dt, nu, nu_density=False, exact
     flat = f_cells.reshape(ncells, nv)
     U_new = transport.dm_update(U, flat, delta, shape, phi, grid.dv)
     fstar = transport.shift(flat, delta, shape).reshape(f_cells.shape)
-    W = bgk.primitive(U_new)
     fnew = np.empty_like(fstar)
     for c in range(ncells):
-        E = bgk.maxwellian(W[c], grid)
-        nuc = nu * W[c, 0] if nu_density else nu
+        E = bgk.conservative_maxwellian(U_new[c], grid)
+        nuc = nu * U_new[c, 0] if nu_density else nu
         fnew[c] = bgk.relax_exact(fstar[c], E, nuc, dt) if exact else bgk.relax_euler(fstar[c], E, nuc, dt)
     return fnew, U_new, s_new, delta, fstar

@@ -48,15 +48,33 @@ def test_bgk_vanishes_at_equilibrium_and_conserves():
     n, L, nu = 32, 8.0, 3.0
     g = make_grid(n, L)
     M = fks_inputs.maxwellian_on_grid(n, L, [1.1], [(0.2, -0.1, 0.3)], [0.9])[0]
-    W = bgk.primitive(moments(M, g))
-    assert np.abs(bgk.bgk_operator(M, W, nu, g)).max() <= 1e-12 * M.max()
+    assert np.abs(bgk.bgk_operator(M, moments(M, g), nu, g)).max() <= 1e-12 * M.max()
     parts = [(0.6, (0.3, 0.0, -0.2), 0.7), (0.5, (-0.4, 0.2, 0.1), 0.9)]
     f = sum(fks_inputs.maxwellian_on_grid(n, L, [r], [u], [T])[0] for r, u, T in parts)
-    W = bgk.primitive(moments(f, g))
-    Q = bgk.bgk_operator(f, W, nu, g)
+    Q = bgk.bgk_operator(f, moments(f, g), nu, g)
     scale = nu * np.abs(f).sum() * g.dv ** 3
-    assert np.abs(moments(Q, g)).max() <= 1e-12 * scale * 10
+    assert np.abs(moments(Q, g)).max() <= 1e-13 * scale
     assert np.abs(Q).max() > 1e-2 * nu * f.max()        # f is far from equilibrium
+
+
+def test_conservative_maxwellian_restores_the_moments():
+    # a coarse grid with a hot, drifting state: the sampled Maxwellian misses U by about
+    # 5e-5 (tails beyond the box); the corrected E has U's moments exactly and differs from
+    # M by a small affine factor in the invariants
+    n, L = 16, 8.0
+    g = make_grid(n, L)
+    f = fks_inputs.maxwellian_on_grid(n, L, [1.0], [(1.5, -1.0, 0.5)], [2.5])[0]
+    f += fks_inputs.maxwellian_on_grid(n, L, [0.5], [(-0.5, 0.5, 0.0)], [0.6])[0]
+    U = moments(f, g)
+    M = bgk.maxwellian(bgk.primitive(U), g)
+    assert np.abs(moments(M, g) - U).max() >= 1e-5 * np.abs(U).max()
+    E = bgk.conservative_maxwellian(U, g)
+    np.testing.assert_allclose(moments(E, g), U, rtol=0, atol=1e-13 * np.abs(U).max())
+    assert np.abs(E - M).max() <= 0.1 * M.max()
+    # fine, well-resolved grid: the correction vanishes
+    g2 = make_grid(32, 8.0)
+    M2 = fks_inputs.maxwellian_on_grid(32, 8.0, [1.0], [(0.2, 0.0, -0.1)], [0.8])[0]
+    np.testing.assert_allclose(bgk.conservative_maxwellian(moments(M2, g2), g2), M2, rtol=0, atol=1e-13 * M2.max())
 
 
 def test_exact_relaxation_properties():
@@ -138,21 +156,16 @@ def test_fks_bgk_step_conserves_and_relaxes():
     tot0 = U.sum(axis=0)
     s = np.zeros((n ** 3, 3))
     f1, U1, s, delta, fstar = fks_step_bgk(f, U, s, g, shape, dx, dt, nu=5.0)
-    # the macroscopic variables after transport are those of f*; relaxation keeps them
-    # up to the discretisation of the Maxwellians on the truncated grid: the moments of
-    # f1 move by (1 - e^{-nu dt}) times that of the sampled Maxwellians
+    # the macroscopic variables after transport are those of f*; the relaxation keeps them
     np.testing.assert_allclose(U1, moments(fstar, g), rtol=0, atol=1e-12 * np.abs(U1).max())
-    W1 = bgk.primitive(U1)
-    mM = np.stack([moments(bgk.maxwellian(W1[c], g), g) for c in range(len(W1))])
-    assert np.abs(mM - U1).max() <= 1e-3 * np.abs(U1).max()
-    np.testing.assert_allclose(moments(f1, g) - U1, -np.expm1(-5.0 * dt) * (mM - U1), rtol=0,
-                               atol=1e-13 * np.abs(U1).max())
-    np.testing.assert_allclose(U1.sum(axis=0)[0], tot0[0], rtol=1e-13)
-    # stiff limit: every cell becomes its Maxwellian
+    np.testing.assert_allclose(moments(f1, g), U1, rtol=0, atol=1e-13 * np.abs(U1).max())
+    np.testing.assert_allclose(U1.sum(axis=0), tot0, rtol=1e-13, atol=1e-13 * np.abs(tot0).max())
+    # stiff limit: every cell becomes its (moment-preserving) Maxwellian
     f2, U2, _, _, _ = fks_step_bgk(f1, U1, s, g, shape, dx, dt, nu=1e5)
     W2 = bgk.primitive(U2)
     for c in range(f2.shape[0]):
-        np.testing.assert_allclose(f2[c], bgk.maxwellian(W2[c], g), rtol=0, atol=1e-14 * f2[c].max())
+        np.testing.assert_allclose(f2[c], bgk.conservative_maxwellian(U2[c], g), rtol=0, atol=1e-14 * f2[c].max())
+        np.testing.assert_allclose(f2[c], bgk.maxwellian(W2[c], g), rtol=0, atol=1e-3 * f2[c].max())
     # the collision frequency does not enter the transported conservative variables
     f3, U3, _, _, _ = fks_step_bgk(f, U, np.zeros((n ** 3, 3)), g, shape, dx, dt, nu=5.0, nu_density=True)
     np.testing.assert_allclose(U3, U1, rtol=0, atol=1e-15 * np.abs(U1).max())

@@ -146,3 +146,13 @@ def test_sigma_form_vanishes_at_equilibrium():
     for v in (np.array([0.0, 0.0, 0.0]), np.array([1.0, -0.5, 0.5])):
         loss_only = sigma_form.collision_integral(lambda p: fun(p), v, 0.25, 1.0)
         assert abs(loss_only) <= 1e-12
+
+
+def test_bkw_input_profile_is_the_pinned_closed_form():
+    # the input module's BKW profile (initial data of the Maxwell-molecule runs, also the
+    # benchmark's closed-form reference) is the oracle's f_bkw, itself pinned above
+    n, L = 16, 8.0
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    for t in (5.5, 6.5):
+        np.testing.assert_allclose(fks_inputs.bkw_initial(n, L, t), bkw.f_bkw(t, V), rtol=1e-14, atol=1e-17)

@@ -80,13 +80,28 @@ def test_angular_rule_converges_second_order():
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.5])
 @pytest.mark.parametrize("s", [0.0, 0.7, 3.3, 9.0])
 @pytest.mark.parametrize("rr", [0.055, 0.12, 3.0])
-def test_radial_g_against_adaptive_quadrature(s, rr):
+def test_radial_g_against_adaptive_quadrature(s, rr, alpha):
+    # eq. Btilde_pl: B~ = 4C (|x|^2 + |y|^2)^{(alpha - 1)/2}
     C = 1.0 / (4 * np.pi)
-    ref = integrate.quad(lambda r: 2 * np.pi * r * 4 * C / np.sqrt(rr ** 2 + r ** 2) * special.j0(r * s),
-                         0.0, R, epsabs=1e-14, limit=400)[0]
-    assert abs(radial_g(np.array([s]), rr, R, 0.0, C)[0] - ref) <= 1e-11 * max(1.0, abs(ref))
+    ref = integrate.quad(lambda r: 2 * np.pi * r * 4 * C * (rr ** 2 + r ** 2) ** (0.5 * (alpha - 1.0))
+                         * special.j0(r * s), 0.0, R, epsabs=1e-14, limit=400)[0]
+    assert abs(radial_g(np.array([s]), rr, R, alpha, C)[0] - ref) <= 1e-11 * max(1.0, abs(ref))
+
+
+def test_vhs_radial_quadrature_at_alpha_one_is_hard_spheres():
+    # at alpha = 1 the power-law kernel is the constant 4C: the radial Gauss-Legendre
+    # terms must rebuild the closed-form hard-sphere tables (phi_R, psi_R), so the two
+    # operators agree to rounding; this pins the alpha dependence of the VHS path
+    import fks_inputs
+    from oracle.collide import collide_fast
+    n, L = 16, 8.0
+    f = fks_inputs.maxwellian_mixture(n, L, 1, seed=3)[0]
+    qh = collide_fast(f, make_plan(n, L, R, a1=3, a2=4, C=0.25))
+    qv = collide_fast(f, make_plan(n, L, R, kernel=VHS, alpha=1.0, a1=3, a2=4, n_radial=16, C=0.25))
+    assert np.linalg.norm(qv - qh) / np.linalg.norm(qh) <= 1e-11
 
 
 def test_tables_are_even_in_k():
