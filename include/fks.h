@@ -100,7 +100,9 @@ fks_status fks_plan_sizes(fks_plan plan, size_t* table_bytes, size_t* workspace_
 fks_status fks_plan_info(fks_plan plan, int32_t* n_terms, int32_t* pad);
 
 /* Binds caller-owned device buffers (sizes from fks_plan_sizes) and enqueues the table
- * upload on `stream`.  May be called again to rebind. */
+ * upload on `stream`.  May be called again to rebind.  d_workspace may be NULL (with
+ * workspace_bytes 0): calls that need the workspace then return FKS_E_STATE (the BGK
+ * steps need none). */
 fks_status fks_plan_bind(fks_plan plan, void* d_tables, size_t table_bytes, void* d_workspace,
                          size_t workspace_bytes, void* stream);
 
@@ -183,6 +185,47 @@ fks_status fks_transport(fks_xport xp, const void* f_in, void* f_out, int32_t dt
  * last step.  The plan's n and dtype must match the transport's grid. */
 fks_status fks_step(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double dt,
                     int32_t n_steps, double* d_moments, void* stream);
+
+/* Options of fks_step_ex.  A zero-initialised struct gives fks_step's behaviour. */
+enum { FKS_COLL_BOLTZMANN = 0, FKS_COLL_BGK = 1 };
+enum { FKS_INT_EULER = 0, FKS_INT_EXP = 1 };
+typedef struct {
+  int32_t collision;  /* FKS_COLL_BOLTZMANN: the plan's spectral Q (Appendix A);
+                         FKS_COLL_BGK: Q = nu (E - f), E the Maxwellian of the cell's
+                         macroscopic variables (Section 2.2.1) */
+  int32_t integrator; /* FKS_INT_EULER: f = f* + dt Q(f*) (eq. disc_relax);
+                         FKS_INT_EXP: the stiff-capable step of Section 2.1's remark:
+                           BGK: E + (f* - E) exp(-nu dt) (exact relaxation at frozen E);
+                           Boltzmann: f = f* + dt_eff Q(f*), dt_eff = (1 - exp(-mu dt)) / mu,
+                           i.e. exp(-mu dt) f* + (1 - exp(-mu dt)) (f* + Q(f*)/mu), bounded for
+                           every dt when mu bounds the collision frequency */
+  double nu;          /* BGK collision frequency, > 0 */
+  int32_t nu_density; /* BGK: 1 -> nu_j = nu * rho_j, 0 -> nu_j = nu */
+  int32_t reserved;
+  double mu;          /* FKS_INT_EXP with the Boltzmann operator: penalty mu > 0 */
+  double* d_cons;     /* [cells][5] FP64 conservative variables U = dv^3 sum phi f, phi = (1, v,
+                         |v|^2/2), in and out: on entry those of f (e.g. from fks_moments), updated
+                         every step by eq. DM_update (Section 3: only the particles that changed
+                         cell contribute).  Required for BGK; optional (NULL) for Boltzmann. */
+  double* d_prim;     /* [cells][5] FP64 out: (rho, u_x, u_y, u_z, T) of the conservative variables
+                         after the last step (ToPrimitive, (3/2) rho T = E - rho |u|^2 / 2);
+                         from d_cons if given, else from the directly recomputed moments. NULL: none */
+  double* d_moments;  /* [cells][5] FP64 out: moments of f after the last step, recomputed directly
+                         from the masses (as in fks_step). NULL: none */
+  void* q_last;       /* [cells][n^3] plan dtype out: the collision operator Q(f*) of the last step
+                         (the increment applied is dt Q for Euler, dt_eff Q for the exponential
+                         Boltzmann step, (1 - exp(-nu dt))/nu Q for exact BGK). NULL: none */
+} fks_step_opts;
+
+/* n_steps steps of the sequential FKS algorithm (Section 4.1) on the whole box, in place on
+ * f: transport (f* = shift(f)), conservative variables by eq. DM_update (if d_cons), then the
+ * collision stage chosen in opts (NULL opts: as fks_step).  f_tmp: caller buffer of f's size,
+ * not overlapping f; after a Boltzmann step it holds f* of the last step (BGK: unspecified).
+ * q_last must not overlap f or f_tmp.  The BGK operator uses the plan only for (n, L, dtype);
+ * the plan need not be bound.  Errors: FKS_E_ARG for invalid options (BGK without d_cons,
+ * nu or mu not positive and finite, unknown enums), as fks_step otherwise. */
+fks_status fks_step_ex(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double dt, int32_t n_steps,
+                       const fks_step_opts* opts, void* stream);
 
 void fks_xport_destroy(fks_xport xp);
 

@@ -8,6 +8,7 @@ every call raises.
 """
 
 import ctypes
+import threading
 
 import torch
 
@@ -15,7 +16,7 @@ from . import _lib
 from ._lib import (FKS_ALLOW_OVERLAP, FKS_CONSERVE, FKS_F32, FKS_F64, FKS_HARD_SPHERES, FKS_VHS,  # noqa: F401
                    FKSError)
 
-__all__ = ["Plan", "Transport", "step", "collide_grouped", "FKSError", "library_path", "profile_start",
+__all__ = ["Plan", "Transport", "step", "step_ex", "collide_grouped", "FKSError", "library_path", "profile_start",
            "profile_stop", "Graph", "Surrogate"]
 
 _DT = {"f32": (FKS_F32, torch.float32), "f64": (FKS_F64, torch.float64)}
@@ -32,6 +33,34 @@ def _stream_ptr(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# Stream capture (Graph): while a graph records on this thread, the wrappers allocate
+# nothing (an allocation inside the recording would be freed when the wrapper returns
+# while the graph keeps writing to it) and every plan, transport and tensor they are given
+# is held by the graph until it is destroyed.
+_capture = threading.local()
+
+
+def _recording():
+    return getattr(_capture, "graph", None)
+
+
+def _hold(*objs):
+    g = _recording()
+    if g is not None:
+        g._keep.extend(o for o in objs if o is not None)
+
+
+def _new_like(t, name):
+    if _recording() is not None:
+        raise FKSError(-1, f"inside a Graph recording, pass {name} explicitly (no allocation while recording)")
+    return torch.empty_like(t)
+
+
+def _no_recording(what):
+    if _recording() is not None:
+        raise FKSError(-1, f"{what} synchronises the host and cannot be recorded in a Graph")
 
 
 class Plan:
@@ -78,18 +107,20 @@ class Plan:
     def collide(self, f, q=None, stream=None):
         cells = self._check_f(f)
         if q is None:
-            q = torch.empty_like(f)
+            q = _new_like(f, "q")
         self._check_f(q, "q")
+        _hold(self, f, q)
         _lib.check(_lib.lib().fks_collide(self._h, _ptr(f), _ptr(q), cells, _stream_ptr(stream)))
         return q
 
     def relax(self, f_in, dt, f_out=None, q=None, moments=None, stream=None):
         cells = self._check_f(f_in, "f_in")
         if f_out is None:
-            f_out = torch.empty_like(f_in)
+            f_out = _new_like(f_in, "f_out")
         self._check_f(f_out, "f_out")
         if q is not None:
             self._check_f(q, "q")
+        _hold(self, f_in, f_out, q, moments)
         if moments is not None and not (moments.is_cuda and moments.dtype == torch.float64
                                         and moments.numel() >= 5 * cells):
             raise FKSError(-1, "moments must be a float64 device tensor with 5 entries per cell")
@@ -116,6 +147,7 @@ class Plan:
 
     def autotune(self, f, q=None, cache_path=None, stream=None):
         """Time the compiled slab schedules on f and keep the fastest (optional cache file)."""
+        _no_recording("autotune")
         cells = self._check_f(f)
         if q is None:
             q = torch.empty_like(f)
@@ -127,7 +159,8 @@ class Plan:
         """n_steps Heun steps of df/dt = Q(f) in place on f (device scratch tmp: 2 buffers)."""
         cells = self._check_f(f)
         if tmp is None:
-            tmp = (torch.empty_like(f), torch.empty_like(f))
+            tmp = (_new_like(f, "tmp"), _new_like(f, "tmp"))
+        _hold(self, f, *tmp)
         _lib.check(_lib.lib().fks_heun(self._h, _ptr(f), _ptr(tmp[0]), _ptr(tmp[1]), float(dt), int(n_steps),
                                        cells, _stream_ptr(stream)))
         return f
@@ -135,7 +168,10 @@ class Plan:
     def moments(self, f, out=None, stream=None):
         cells = self._check_f(f)
         if out is None:
+            if _recording() is not None:
+                raise FKSError(-1, "inside a Graph recording, pass out explicitly")
             out = torch.empty((cells, 5), dtype=torch.float64, device=f.device)
+        _hold(self, f, out)
         _lib.check(_lib.lib().fks_moments(self._h, _ptr(f), cells, _ptr(out), _stream_ptr(stream)))
         return out
 
@@ -206,6 +242,9 @@ class Surrogate:
     def features(self, plan, f, x=None, rho=None, mom=None, stream=None):
         """(x, rho, mom): BF16 features, FP32 densities and FP64 moments of f."""
         cells = plan._check_f(f)
+        if _recording() is not None and (x is None or rho is None or mom is None):
+            raise FKSError(-1, "inside a Graph recording, pass x, rho and mom explicitly")
+        _hold(self, plan, f, x, rho, mom)
         if x is None:
             x = torch.empty((cells, self.n_in), dtype=torch.bfloat16, device=f.device)
         if rho is None:
@@ -223,7 +262,8 @@ class Surrogate:
     def targets(self, plan, q, rho, mom=None, t=None, stream=None):
         cells = q.numel() // self.n_out
         if t is None:
-            t = torch.empty_like(q)
+            t = _new_like(q, "t")
+        _hold(self, plan, q, rho, mom, t)
         _lib.check(_lib.lib().fks_sur_targets(self._h, plan.handle, _ptr(q), _ptr(rho), _ptr(mom), _ptr(t), cells,
                                               _stream_ptr(stream)))
         return t
@@ -231,7 +271,10 @@ class Surrogate:
     def forward(self, x, y=None, stream=None):
         batch = x.shape[0]
         if y is None:
+            if _recording() is not None:
+                raise FKSError(-1, "inside a Graph recording, pass y explicitly")
             y = torch.empty((batch, self.n_out), dtype=torch.float32, device=x.device)
+        _hold(self, x, y)
         _lib.check(_lib.lib().fks_sur_forward(self._h, _ptr(x), _ptr(y), batch, _stream_ptr(stream)))
         return y
 
@@ -239,6 +282,7 @@ class Surrogate:
         """One forward/backward (and Adam step if update); returns the device loss tensor."""
         batch = x.shape[0]
         loss = self._loss if loss is None else loss
+        _hold(self, x, t, loss)
         _lib.check(_lib.lib().fks_sur_train_step(self._h, _ptr(x), _ptr(t), batch, float(lr), int(bool(update)),
                                                  _ptr(loss), _stream_ptr(stream)))
         return loss
@@ -246,6 +290,7 @@ class Surrogate:
     def infer(self, plan, f, q=None, threshold=1e-3, indicator=None, stream=None):
         """Q of FP32 cells f: surrogate, indicator, spectral fallback where it exceeds
         threshold (threshold < 0: none).  Returns (q, number of fallback cells)."""
+        _no_recording("Surrogate.infer")
         cells = plan._check_f(f)
         if q is None:
             q = torch.empty_like(f)
@@ -289,7 +334,8 @@ class Transport:
 
     def __call__(self, f_in, f_out=None, dt=0.0, stream=None):
         if f_out is None:
-            f_out = torch.empty_like(f_in)
+            f_out = _new_like(f_in, "f_out")
+        _hold(self, f_in, f_out)
         code = FKS_F32 if f_in.dtype == torch.float32 else FKS_F64
         _lib.check(_lib.lib().fks_transport(self._h, _ptr(f_in), _ptr(f_out), code, float(dt),
                                             _stream_ptr(stream)))
@@ -305,9 +351,40 @@ class Transport:
 def step(plan, xport, f, dt, n_steps=1, f_tmp=None, moments=None, stream=None):
     """n_steps split steps (transport, then Euler collision) in place on f."""
     if f_tmp is None:
-        f_tmp = torch.empty_like(f)
+        f_tmp = _new_like(f, "f_tmp")
+    _hold(plan, xport, f, f_tmp, moments)
     _lib.check(_lib.lib().fks_step(plan.handle, xport.handle, _ptr(f), _ptr(f_tmp), float(dt), int(n_steps),
                                    _ptr(moments), _stream_ptr(stream)))
+    return f
+
+
+def _check_cells5(t, cells, name):
+    if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                              and t.numel() >= 5 * cells):
+        raise FKSError(-1, f"{name} must be a contiguous float64 device tensor with 5 entries per cell")
+
+
+def step_ex(plan, xport, f, dt, n_steps=1, f_tmp=None, collision="boltzmann", integrator="euler", nu=0.0,
+            nu_density=False, mu=0.0, cons=None, prim=None, moments=None, q_last=None, stream=None):
+    """n_steps FKS steps in place on f with the options of fks_step_ex: collision "boltzmann" or
+    "bgk" (frequency nu, times the density if nu_density), integrator "euler" or "exp"
+    (penalty mu for Boltzmann), conservative variables cons (in/out, eq. DM_update), primitive
+    variables prim, direct moments, and the collision operator of the last step q_last."""
+    cells = plan._check_f(f)
+    if f_tmp is None:
+        f_tmp = _new_like(f, "f_tmp")
+    plan._check_f(f_tmp, "f_tmp")
+    _hold(plan, xport, f, f_tmp, cons, prim, moments, q_last)
+    if q_last is not None:
+        plan._check_f(q_last, "q_last")
+    for t, name in ((cons, "cons"), (prim, "prim"), (moments, "moments")):
+        _check_cells5(t, cells, name)
+    o = _lib.StepOpts(collision={"boltzmann": _lib.FKS_COLL_BOLTZMANN, "bgk": _lib.FKS_COLL_BGK}[collision],
+                      integrator={"euler": _lib.FKS_INT_EULER, "exp": _lib.FKS_INT_EXP}[integrator],
+                      nu=float(nu), nu_density=int(bool(nu_density)), reserved=0, mu=float(mu),
+                      d_cons=_ptr(cons), d_prim=_ptr(prim), d_moments=_ptr(moments), q_last=_ptr(q_last))
+    _lib.check(_lib.lib().fks_step_ex(plan.handle, xport.handle, _ptr(f), _ptr(f_tmp), float(dt), int(n_steps),
+                                      ctypes.byref(o), _stream_ptr(stream)))
     return f
 
 
@@ -315,7 +392,8 @@ def collide_grouped(plans, fs, qs=None, stream=None):
     """Uneven batch: group g evaluates Q on fs[g] with plans[g] (one call, one stream)."""
     g = len(plans)
     if qs is None:
-        qs = [torch.empty_like(f) for f in fs]
+        qs = [_new_like(f, "qs") for f in fs]
+    _hold(*plans, *fs, *qs)
     cells = [p._check_f(f) for p, f in zip(plans, fs)]
     VP = ctypes.c_void_p
     arr_p = (VP * g)(*[p.handle for p in plans])
@@ -348,17 +426,26 @@ class Graph:
     def __init__(self, stream=None):
         self.stream = torch.cuda.current_stream() if stream is None else stream
         self._h = None
+        self._keep = []     # plans, transports and tensors the recording uses
 
     def __enter__(self):
+        if _recording() is not None:
+            raise FKSError(-1, "a Graph is already recording on this thread")
         _lib.check(_lib.lib().fks_graph_begin(_stream_ptr(self.stream)))
+        _capture.graph = self
         return self
 
     def __exit__(self, exc_type, exc, tb):
+        _capture.graph = None
         h = ctypes.c_void_p()
         status = _lib.lib().fks_graph_end(_stream_ptr(self.stream), ctypes.byref(h))
         if exc_type is None:
             _lib.check(status)
             self._h = h
+        else:
+            if status == 0:
+                _lib.lib().fks_graph_destroy(h)
+            self._keep = []
         return False
 
     def launch(self):
@@ -369,3 +456,4 @@ class Graph:
         if h is not None and _lib._lib is not None:
             _lib._lib.fks_graph_destroy(h)
             self._h = None
+        self._keep = []

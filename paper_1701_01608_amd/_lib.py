@@ -31,6 +31,17 @@ class CollideDesc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
+class StepOpts(ctypes.Structure):
+    _fields_ = [("collision", ctypes.c_int32), ("integrator", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("nu_density", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("d_cons", ctypes.c_void_p), ("d_prim", ctypes.c_void_p), ("d_moments", ctypes.c_void_p),
+                ("q_last", ctypes.c_void_p)]
+
+
+FKS_COLL_BOLTZMANN, FKS_COLL_BGK = 0, 1
+FKS_INT_EULER, FKS_INT_EXP = 0, 1
+
+
 class ProfileStats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
@@ -68,6 +79,8 @@ _SIGS = {
     "fks_xport_bind": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "fks_transport": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_double, _VP]),
     "fks_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, _VP, _VP]),
+    "fks_step_ex": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(StepOpts),
+                                   _VP]),
     "fks_xport_destroy": (None, [_VP]),
     "fks_sur_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.c_float, ctypes.c_uint32, ctypes.POINTER(_VP)]),

@@ -32,6 +32,8 @@ FFT_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only", "-fno-math-errno", "-ffp
 EXACT_FLAGS = ["-ffp-contract=off"]
 
 SOURCES = [
+    ("fks_collide_f32.hip", FFT_FLAGS),
+    ("fks_collide_f64.hip", FFT_FLAGS),
     ("fks_collide.hip", FFT_FLAGS),
     ("fks_transport.hip", EXACT_FLAGS),
     ("fks_surrogate.hip", ["-fno-math-errno"]),

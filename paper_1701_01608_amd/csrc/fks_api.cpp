@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -154,7 +155,7 @@ struct fks_plan_s {
   size_t ws_bytes = 0;
   bool bound = false;
   // workspace carve-up (byte offsets)
-  size_t off_fhat = 0, off_scr = 0, off_g = 0, off_d = 0;
+  size_t off_fhat = 0, off_scr = 0, off_d = 0;
   // slab schedule (index into geo.variant_slabs) and workgroup-to-XCD mapping
   int variant = 0;
   int xcd_map = 1;
@@ -372,22 +373,41 @@ int effective_groups(int n_terms, int tg) {
   return (n_terms + tpg - 1) / tpg;
 }
 
-fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, void* f_out, double dt,
-                       int64_t n_cells, double* moments, void* stream) {
+// Workspace regions of one chunk of `cells` cells: fhat, the forward/finish scratch, slab
+// partials (for the plan's term groups).
+struct WsLayout {
+  size_t off_fhat, off_scr, off_d, bytes;
+};
+WsLayout ws_layout(const fks_plan_s* p, int64_t cells, int groups) {
+  const size_t cs = p->esize * 2;  // complex element
+  WsLayout w{};
+  size_t off = 0;
+  w.off_fhat = off;
+  off = round256(off + size_t(cells) * p->geo.fhat_elems * cs);
+  w.off_scr = off;
+  off = round256(off + size_t(cells) * p->geo.scratch_elems * cs);
+  w.off_d = off;
+  off = round256(off + size_t(cells) * groups * p->geo.d_elems * cs);
+  w.bytes = off;
+  return w;
+}
+
+fks_status run_collide_in(fks_plan_s* p, void* ws_base, const WsLayout& w, int64_t chunk, const void* f,
+                          const void* f_in, void* q, void* f_out, double dt, int64_t n_cells, double* moments,
+                          void* stream) {
   const size_t cell_bytes = size_t(p->n) * p->n * p->n * p->esize;
   const int f32 = p->d.dtype == FKS_F32;
-  for (int64_t c0 = 0; c0 < n_cells; c0 += p->max_cells) {
-    const int64_t c = (n_cells - c0 < p->max_cells) ? (n_cells - c0) : p->max_cells;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += chunk) {
+    const int64_t c = (n_cells - c0 < chunk) ? (n_cells - c0) : chunk;
     fks::CollideArgs a{};
     a.f = static_cast<const unsigned char*>(f) + size_t(c0) * cell_bytes;
     a.tables = p->d_tables;
     a.n_terms = p->n_terms;
     a.n_cells = c;
-    unsigned char* ws = static_cast<unsigned char*>(p->d_ws);
-    a.ws_fhat = ws + p->off_fhat;
-    a.ws_scratch = ws + p->off_scr;
-    a.ws_g = ws + p->off_g;
-    a.ws_d = ws + p->off_d;
+    unsigned char* ws = static_cast<unsigned char*>(ws_base);
+    a.ws_fhat = ws + w.off_fhat;
+    a.ws_scratch = ws + w.off_scr;
+    a.ws_d = ws + w.off_d;
     a.f_in = f_in ? static_cast<const unsigned char*>(f_in) + size_t(c0) * cell_bytes : nullptr;
     a.q = q ? static_cast<unsigned char*>(q) + size_t(c0) * cell_bytes : nullptr;
     a.f_out = f_out ? static_cast<unsigned char*>(f_out) + size_t(c0) * cell_bytes : nullptr;
@@ -402,6 +422,14 @@ fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, 
     if (s != FKS_OK) return s;
   }
   return ok();
+}
+
+// Q / Euler over n_cells cells in chunks of max_cells through the plan's bound workspace.
+fks_status run_collide(fks_plan_s* p, const void* f, const void* f_in, void* q, void* f_out, double dt,
+                       int64_t n_cells, double* moments, void* stream) {
+  if (!p->d_ws) return fail(FKS_E_STATE, "plan workspace not bound (fks_plan_bind with a workspace)");
+  const WsLayout w{p->off_fhat, p->off_scr, p->off_d, p->ws_bytes};
+  return run_collide_in(p, p->d_ws, w, p->max_cells, f, f_in, q, f_out, dt, n_cells, moments, stream);
 }
 
 bool ranges_overlap(const void* a, const void* b, size_t bytes) {
@@ -527,18 +555,12 @@ fks_status fks_plan_create(const fks_collide_desc* desc, int64_t max_cells, fks_
     delete p;
     return fail(FKS_E_ARG, "singular invariant Gram matrix");
   }
-  const size_t cs = p->esize * 2;  // complex element
-  size_t off = 0;
-  p->off_fhat = off;
-  off = round256(off + size_t(max_cells) * p->geo.fhat_elems * cs);
-  p->off_scr = off;
-  off = round256(off + size_t(max_cells) * p->geo.scratch_elems * cs);
   p->tg_max = (max_cells <= kSmallBatch) ? (p->n_terms < kMaxTermGroups ? p->n_terms : kMaxTermGroups) : 1;
-  p->off_g = off;
-  off = round256(off + size_t(max_cells) * p->tg_max * p->geo.g_elems * p->esize);
-  p->off_d = off;
-  off = round256(off + size_t(max_cells) * p->tg_max * p->geo.d_elems * cs);
-  p->ws_bytes = off;
+  const WsLayout w = ws_layout(p, max_cells, p->tg_max);
+  p->off_fhat = w.off_fhat;
+  p->off_scr = w.off_scr;
+  p->off_d = w.off_d;
+  p->ws_bytes = w.bytes;
   *out = p;
   return ok();
 }
@@ -559,11 +581,13 @@ fks_status fks_plan_info(fks_plan p, int32_t* n_terms, int32_t* pad) {
 
 fks_status fks_plan_bind(fks_plan p, void* d_tables, size_t table_bytes, void* d_workspace, size_t workspace_bytes,
                          void* stream) {
-  if (!p || !d_tables || !d_workspace) return fail(FKS_E_ARG, "null argument");
-  if (!aligned(d_tables) || !aligned(d_workspace)) return fail(FKS_E_ARG, "buffers must be 256-byte aligned");
+  if (!p || !d_tables) return fail(FKS_E_ARG, "null argument");
+  if (!d_workspace && workspace_bytes != 0) return fail(FKS_E_ARG, "null workspace with a nonzero size");
+  if (!aligned(d_tables) || (d_workspace && !aligned(d_workspace)))
+    return fail(FKS_E_ARG, "buffers must be 256-byte aligned");
   if (table_bytes < p->host_tables.size())
     return fail(FKS_E_WORKSPACE, "table buffer %zu < %zu bytes", table_bytes, p->host_tables.size());
-  if (workspace_bytes < p->ws_bytes)
+  if (d_workspace && workspace_bytes < p->ws_bytes)
     return fail(FKS_E_WORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, p->ws_bytes);
   fks_status s = check_hip(hipMemcpyAsync(d_tables, p->host_tables.data(), p->host_tables.size(),
                                           hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)),
@@ -735,9 +759,12 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
   std::snprintf(keybuf, sizeof(keybuf), "\"device\":\"%s\",\"n\":%d,\"dtype\":\"%s\",\"terms\":%d,\"cells\":%lld",
                 device_name().c_str(), p->n, p->d.dtype == FKS_F32 ? "f32" : "f64", p->n_terms,
                 static_cast<long long>(n_cells));
+  // the stored line continues with ',"slabs":', so matching the key plus its comma compares the
+  // cell count exactly (4096 does not match a line written for 40960)
   const std::string key(keybuf);
+  const std::string match = key + ",";
   int cs = 0, cx = 0, ct = 1;
-  if (cache_path && cache_lookup(cache_path, key, &cs, &cx, &ct) && fks_plan_set_schedule(p, cs, cx) == FKS_OK &&
+  if (cache_path && cache_lookup(cache_path, match, &cs, &cx, &ct) && fks_plan_set_schedule(p, cs, cx) == FKS_OK &&
       fks_plan_set_term_groups(p, ct) == FKS_OK)
     return ok();
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1056,6 +1083,7 @@ fks_status fks_sur_features(fks_sur s, fks_plan p, const void* f, void* x, float
     return st == FKS_OK ? ok() : st;
   }
   // other grids: full transform, then the low modes
+  if (!p->d_ws) return fail(FKS_E_STATE, "plan workspace not bound (fks_plan_bind with a workspace)");
   const double box3 = 8.0 * p->d.L * p->d.L * p->d.L;
   unsigned char* ws = static_cast<unsigned char*>(p->d_ws);
   for (int64_t c0 = 0; c0 < n_cells; c0 += p->max_cells) {
@@ -1328,6 +1356,92 @@ fks_status fks_step(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt, in
     if (s != FKS_OK) return s;
   }
   return ok();
+}
+
+fks_status fks_step_ex(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt, int32_t n_steps,
+                       const fks_step_opts* opts, void* stream) {
+  fks_step_opts o{};
+  if (opts) o = *opts;
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (o.collision != FKS_COLL_BOLTZMANN && o.collision != FKS_COLL_BGK) return fail(FKS_E_ARG, "unknown collision");
+  if (o.integrator != FKS_INT_EULER && o.integrator != FKS_INT_EXP) return fail(FKS_E_ARG, "unknown integrator");
+  const bool bgk = o.collision == FKS_COLL_BGK;
+  if (!bgk) {
+    fks_status s = check_plan_ready(p);
+    if (s != FKS_OK) return s;
+  }
+  if (!x) return fail(FKS_E_ARG, "null transport");
+  if (!x->bound) return fail(FKS_E_STATE, "transport state not bound");
+  if (x->n != p->n || std::fabs(x->L - p->d.L) > 0.0) return fail(FKS_E_ARG, "plan and transport grids differ");
+  if (!f || !f_tmp) return fail(FKS_E_ARG, "null f or f_tmp");
+  if (n_steps < 0) return fail(FKS_E_ARG, "n_steps < 0");
+  if (!std::isfinite(dt)) return fail(FKS_E_ARG, "dt must be finite");
+  if (bgk && (!(o.nu > 0.0) || !std::isfinite(o.nu))) return fail(FKS_E_ARG, "BGK needs nu > 0");
+  if (bgk && !o.d_cons) return fail(FKS_E_ARG, "BGK needs the conservative variables d_cons");
+  if (!bgk && o.integrator == FKS_INT_EXP && (!(o.mu > 0.0) || !std::isfinite(o.mu)))
+    return fail(FKS_E_ARG, "the exponential Boltzmann step needs mu > 0");
+  const int64_t cells = int64_t(x->nx) * x->ny * x->nz;
+  const size_t bytes = size_t(cells) * p->n * p->n * p->n * p->esize;
+  if (ranges_overlap(f, f_tmp, bytes)) return fail(FKS_E_ARG, "f_tmp must not overlap f");
+  if (o.q_last && (ranges_overlap(o.q_last, f, bytes) || ranges_overlap(o.q_last, f_tmp, bytes)))
+    return fail(FKS_E_ARG, "q_last must not overlap f or f_tmp");
+  if (n_steps == 0) return ok();
+  const int f32 = p->d.dtype == FKS_F32;
+  const fks::XportState xs = xport_state(x);
+  fks::StepCellArgs a{};
+  a.n = p->n;
+  a.L = p->d.L;
+  a.nx = x->nx;
+  a.ny = x->ny;
+  a.nz = x->nz;
+  a.cons = o.d_cons;
+  a.prim = o.d_prim;
+  a.nu = o.nu;
+  a.nu_density = o.nu_density ? 1 : 0;
+  a.dt = dt;
+  fks_status s = FKS_OK;
+  if (bgk) {
+    // ping-pong between f and f_tmp; the fused kernel shifts, updates U and relaxes
+    const int mode = o.integrator == FKS_INT_EXP ? 2 : 1;
+    void* cur = f;
+    void* nxt = f_tmp;
+    for (int st = 0; st < n_steps && s == FKS_OK; ++st) {
+      const bool last = st == n_steps - 1;
+      s = check_hip(fks::launch_xport_advance(xs, x->n, x->L, dt, x->dx, stream), "transport advance");
+      if (s != FKS_OK) break;
+      a.q = last ? o.q_last : nullptr;
+      a.moments = last ? o.d_moments : nullptr;
+      s = check_hip(fks::launch_step_cell(f32, cur, nxt, xs.dl, 1, mode, a, stream), "BGK step");
+      std::swap(cur, nxt);
+    }
+    if (s == FKS_OK && cur != f)
+      s = check_hip(fks::launch_copy(f32, cur, f, cells * int64_t(p->n) * p->n * p->n, stream), "copy back");
+    return s == FKS_OK ? ok() : s;
+  }
+  const double dt_eff = o.integrator == FKS_INT_EXP ? -std::expm1(-o.mu * dt) / o.mu : dt;
+  for (int st = 0; st < n_steps; ++st) {
+    const bool last = st == n_steps - 1;
+    s = check_hip(fks::launch_xport_advance(xs, x->n, x->L, dt, x->dx, stream), "transport advance");
+    if (s != FKS_OK) return s;
+    if (o.d_cons) {
+      a.q = nullptr;
+      a.moments = nullptr;
+      a.prim = last ? o.d_prim : nullptr;
+      s = check_hip(fks::launch_step_cell(f32, f, f_tmp, xs.dl, 1, 0, a, stream), "transport + DM update");
+    } else {
+      s = check_hip(fks::launch_roll(f32, f, f_tmp, xs.dl, x->n * x->n * x->n, x->nx, x->ny, x->nz, stream),
+                    "transport roll");
+    }
+    if (s != FKS_OK) return s;
+    double* mom = nullptr;
+    if (last) mom = o.d_moments ? o.d_moments : (o.d_prim && !o.d_cons ? o.d_prim : nullptr);
+    s = run_collide(p, f_tmp, f_tmp, last ? o.q_last : nullptr, f, dt_eff, cells, mom, stream);
+    if (s != FKS_OK) return s;
+  }
+  if (o.d_prim && !o.d_cons)
+    s = check_hip(fks::launch_to_primitive(o.d_moments ? o.d_moments : o.d_prim, o.d_prim, cells, stream),
+                  "to primitive");
+  return s == FKS_OK ? ok() : s;
 }
 
 void fks_xport_destroy(fks_xport x) { delete x; }

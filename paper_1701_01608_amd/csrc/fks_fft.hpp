@@ -241,6 +241,65 @@ __device__ __forceinline__ void fold_half(cpx<T>* u, Load&& load) {
   });
 }
 
+// The same split into R parts (R divides n): outputs X[R j + h], j < n/R, from the
+// n/R-point inverse DFT of u[k'] = w^{k' h} sum_{q < R} c[k' + q n/R] exp(2 pi i q h / R).
+// R = 2 is fold_half.  More parts hold fewer values per thread (n/R) at the price of
+// every part reading all nonzero inputs.
+template <int n, int R, int kh, int h, typename T, class Load>
+__device__ __forceinline__ void fold_part(cpx<T>* u, Load&& load) {
+  static_assert(n % R == 0, "parts must divide the length");
+  constexpr int m = n / R;
+  static_for<0, m>([&](auto kk) {
+    constexpr int kp = decltype(kk)::value;
+    cpx<T> v = {T(0), T(0)};
+    bool any = false;
+    static_for<0, R>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      constexpr int pos = kp + q * m;
+      if constexpr ((pos <= kh) || (pos >= n - kh)) {
+        constexpr int idx = (pos <= kh ? pos : pos - n) + kh;
+        const cpx<T> c = twiddle<R, +1, long(q) * h>(load(idx));
+        v = any ? v + c : c;
+        any = true;
+      }
+    });
+    u[kp] = twiddle<n, +1, long(kp) * h>(v);
+    if constexpr (kp % 6 == 5) sched_fence();
+  });
+}
+
+// Forward (sign -1) counterpart with every input present: outputs Y[R j + h], j < n/R, of
+// Y[k] = sum_y a[y] exp(-2 pi i y k / n) from the n/R-point forward DFT of
+// u[k'] = w^{-k' h} sum_{q < R} a[k' + q n/R] exp(-2 pi i q h / R); load(i) returns a[i].
+template <int n, int R, int h, typename T, class Load>
+__device__ __forceinline__ void fold_part_fwd(cpx<T>* u, Load&& load) {
+  static_assert(n % R == 0, "parts must divide the length");
+  constexpr int m = n / R;
+  static_for<0, m>([&](auto kk) {
+    constexpr int kp = decltype(kk)::value;
+    cpx<T> v = load(kp);
+    static_for<1, R>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      v = v + twiddle<R, -1, long(q) * h>(load(kp + q * m));
+    });
+    u[kp] = twiddle<n, -1, long(kp) * h>(v);
+    if constexpr (kp % 6 == 5) sched_fence();
+  });
+}
+
+// f(std::integral_constant<int, h>) for a run-time part index h < R, as one if/else chain:
+// exactly one part's code runs (independent ifs may be if-converted into selects that
+// evaluate every part, with all of their loads live at once)
+template <int R, int H = 0, class F>
+__device__ __forceinline__ void part_dispatch(int h, F&& f) {
+  if constexpr (H == R - 1) {
+    f(std::integral_constant<int, H>{});
+  } else {
+    if (h == H) f(std::integral_constant<int, H>{});
+    else part_dispatch<R, H + 1>(h, f);
+  }
+}
+
 template <int n, int kh, int h, typename T, class Load>
 __device__ __forceinline__ void idft_half(cpx<T>* u, Load&& load) {
   fold_half<n, kh, h>(u, load);

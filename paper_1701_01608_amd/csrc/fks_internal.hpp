@@ -24,7 +24,6 @@ struct CollideArgs {
   int64_t n_cells;
   void* ws_fhat;
   void* ws_scratch;
-  void* ws_g;
   void* ws_d;
   const void* f_in;  // Euler base (may equal f), or null
   void* q;           // Q output or null
@@ -44,7 +43,6 @@ struct SlabGeometry {
   int variant_slabs[2];  // slab count S of each schedule
   size_t fhat_elems;     // complex elements per cell
   size_t scratch_elems;  // complex elements per cell
-  size_t g_elems;        // real elements per cell
   size_t d_elems;        // complex elements per cell
   int npair;             // half-plane z pencils, (K^2 + 1)/2
   int table_rows;        // k_z rows of fhat and of each table term (k_z = row - n/2)
@@ -105,5 +103,24 @@ hipError_t launch_xport_reset(const XportState& st, int nv, void* stream);
 hipError_t launch_xport_advance(const XportState& st, int n, double L, double dt, double dx, void* stream);
 hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int nv, int nx,
                        int ny, int nz, void* stream);
+
+// per-cell transport with eq. DM_update / ToPrimitive and optional BGK relaxation
+struct StepCellArgs {
+  int n;
+  double L;
+  int nx, ny, nz;
+  double* cons;      // [cells][5] conservative variables, updated in place (DM mode)
+  double* prim;      // [cells][5] (rho, u, T) out, or null
+  double nu;         // BGK collision frequency (scale)
+  int nu_density;    // nu_j = nu * rho_j
+  double dt;
+  void* q;           // BGK: nu (E - f*) out, or null
+  double* moments;   // direct moments of the output masses, or null
+};
+// mode 0: shift only; 1: BGK Euler; 2: BGK exact relaxation (modes 1, 2 need dm)
+hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int dm, int mode,
+                            const StepCellArgs& a, void* stream);
+hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream);
+hipError_t launch_copy(int dtype_is_f32, const void* src, void* dst, int64_t n, void* stream);
 
 }  // namespace fks

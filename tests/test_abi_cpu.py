@@ -156,3 +156,20 @@ def test_term_groups_limits(lib):
     assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
     assert tg.value == 6
     L.fks_plan_destroy(small)
+
+
+def test_step_ex_validates_options_on_the_host(lib):
+    L = lib.lib()
+    st, h = _create(lib, _desc(lib))
+    assert st == 0
+    ok = lib.StepOpts()
+    # no plan; unknown enums; missing transport: rejected before any device work
+    assert L.fks_step_ex(None, None, None, None, 0.01, 1, ctypes.byref(ok), None) == -1
+    for bad in (lib.StepOpts(collision=7), lib.StepOpts(integrator=9)):
+        assert L.fks_step_ex(h, None, None, None, 0.01, 1, ctypes.byref(bad), None) == -1
+        assert L.fks_last_error()
+    bgk = lib.StepOpts(collision=lib.FKS_COLL_BGK, nu=1.0)
+    assert L.fks_step_ex(h, None, None, None, 0.01, 1, ctypes.byref(bgk), None) == -1   # null transport
+    # the Boltzmann operator needs a bound plan
+    assert L.fks_step_ex(h, None, None, None, 0.01, 1, ctypes.byref(ok), None) == -5
+    L.fks_plan_destroy(h)

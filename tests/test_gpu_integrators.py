@@ -111,3 +111,35 @@ def test_heun_on_a_batch_beyond_the_bounded_grid():
         got = f[c].double().cpu().numpy()
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert err <= 1e-6, (c, err)
+
+
+def test_graph_recording_allocates_nothing_and_holds_its_buffers():
+    # inside a recording the wrappers refuse to allocate (the allocation would be freed
+    # while the graph keeps writing to it) and keep every buffer alive with the graph
+    import gc
+    from paper_1701_01608_amd import FKSError, Graph
+    plan = _plan()
+    f0 = torch.tensor(fks_inputs.bkw_initial(N, L, 5.5)[None], device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with pytest.raises(FKSError):
+            with Graph(s):
+                plan.collide(f0, stream=s)            # q omitted
+    q = torch.empty_like(f0)
+    fin = f0.clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with Graph(s) as g:
+            plan.collide(fin, q, stream=s)
+    fin_id = id(fin)
+    del fin                                           # now only the graph refers to it
+    gc.collect()
+    assert any(id(t) == fin_id for t in g._keep)
+    assert any(t is q for t in g._keep) and any(o is plan for o in g._keep)
+    with torch.cuda.stream(s):
+        g.launch()
+    s.synchronize()
+    ref = plan.collide(f0)
+    torch.cuda.synchronize()
+    assert torch.equal(q, ref)
