@@ -101,8 +101,8 @@ fks_status fks_plan_info(fks_plan plan, int32_t* n_terms, int32_t* pad);
 
 /* Binds caller-owned device buffers (sizes from fks_plan_sizes) and enqueues the table
  * upload on `stream`.  May be called again to rebind.  d_workspace may be NULL (with
- * workspace_bytes 0): calls that need the workspace then return FKS_E_STATE (the BGK
- * steps need none). */
+ * workspace_bytes 0): only fks_collide_noalloc and the BGK steps can then run; calls that
+ * need the workspace return FKS_E_STATE. */
 fks_status fks_plan_bind(fks_plan plan, void* d_tables, size_t table_bytes, void* d_workspace,
                          size_t workspace_bytes, void* stream);
 
@@ -111,6 +111,18 @@ fks_status fks_plan_bind(fks_plan plan, void* d_tables, size_t table_bytes, void
  * dtype; q must not overlap f.  With FKS_CONSERVE, q is projected in FP64 so its discrete
  * mass, momentum and energy vanish.  n_cells may exceed max_cells (processed in chunks). */
 fks_status fks_collide(fks_plan plan, const void* f, void* q, int64_t n_cells, void* stream);
+
+/* fks_collide for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same q = Q(f) with the same
+ * kernels, but the transform workspace is a fixed 128 MiB array owned by the library (one
+ * per GPU, held until the process ends) instead of the plan's bound workspace.  The plan
+ * needs only its tables bound (fks_plan_bind may pass a NULL workspace of 0 bytes).  The call
+ * allocates nothing.  n_cells is limited to what the array holds for the plan (at n = 32 FP32
+ * about 230 cells) and to max_cells; larger batches return FKS_E_ARG with the limit in the
+ * message.  Every call on one GPU uses the same array: calls that overlap on a GPU (other
+ * streams, other host threads) race and must be ordered by the caller.  Errors as
+ * fks_collide; FKS_E_STATE if the tables are not bound. */
+fks_status fks_collide_noalloc(fks_plan plan, const void* f, void* q, int64_t n_cells, void* stream);
 
 /* Explicit Euler collision stage (eq. disc_relax): f_out = f_in + dt * Q(f_in) per cell.
  * f_out may equal f_in (in place).  q (optional, NULL to skip) receives Q.  d_moments

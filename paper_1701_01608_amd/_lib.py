@@ -58,6 +58,7 @@ _SIGS = {
     "fks_plan_info": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "fks_plan_bind": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.c_size_t, _VP]),
     "fks_collide": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fks_collide_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fks_relax": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int64, _VP, _VP]),
     "fks_moments": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
     "fks_heun": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, _VP]),

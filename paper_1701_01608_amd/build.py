@@ -37,6 +37,7 @@ SOURCES = [
     ("fks_collide.hip", FFT_FLAGS),
     ("fks_transport.hip", EXACT_FLAGS),
     ("fks_surrogate.hip", ["-fno-math-errno"]),
+    ("fks_noalloc.hip", []),
     ("fks_api.cpp", EXACT_FLAGS),
 ]
 

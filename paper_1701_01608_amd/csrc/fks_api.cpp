@@ -614,6 +614,32 @@ fks_status fks_collide(fks_plan p, const void* f, void* q, int64_t n_cells, void
   return run_collide(p, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
 }
 
+fks_status fks_collide_noalloc(fks_plan p, const void* f, void* q, int64_t n_cells, void* stream) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (!p->d_tables) return fail(FKS_E_STATE, "plan tables not bound (call fks_plan_bind)");
+  if (n_cells < 0) return fail(FKS_E_ARG, "n_cells < 0");
+  if (n_cells == 0) return ok();
+  if (!f || !q) return fail(FKS_E_ARG, "null f or q");
+  const size_t bytes = size_t(n_cells) * p->n * p->n * p->n * p->esize;
+  if (ranges_overlap(f, q, bytes)) return fail(FKS_E_ARG, "q must not overlap f");
+  const int groups = effective_groups(p->n_terms, p->tg);
+  const WsLayout w = ws_layout(p, n_cells, groups);
+  if (n_cells > p->max_cells || w.bytes > fks::kNoAllocScratchBytes) {
+    // the largest cell count whose layout fits: start from the unrounded per-cell bytes
+    const size_t per_cell = (p->geo.fhat_elems + p->geo.scratch_elems + size_t(groups) * p->geo.d_elems) * p->esize * 2;
+    int64_t cap = int64_t(fks::kNoAllocScratchBytes / per_cell);
+    while (cap > 0 && ws_layout(p, cap, groups).bytes > fks::kNoAllocScratchBytes) --cap;
+    while (ws_layout(p, cap + 1, groups).bytes <= fks::kNoAllocScratchBytes) ++cap;
+    if (cap > p->max_cells) cap = p->max_cells;
+    return fail(FKS_E_ARG, "n_cells = %lld exceeds what the %zu MiB library scratch holds for this plan (%lld cells)",
+                static_cast<long long>(n_cells), fks::kNoAllocScratchBytes >> 20, static_cast<long long>(cap));
+  }
+  void* scratch = nullptr;
+  fks_status s = check_hip(fks::noalloc_scratch(&scratch), "library scratch address");
+  if (s != FKS_OK) return s;
+  return run_collide_in(p, scratch, w, n_cells, f, nullptr, q, nullptr, 0.0, n_cells, nullptr, stream);
+}
+
 fks_status fks_relax(fks_plan p, const void* f_in, void* f_out, void* q, double dt, int64_t n_cells,
                      double* d_moments, void* stream) {
   fks_status s = check_plan_ready(p);

@@ -90,6 +90,11 @@ hipError_t launch_compact(const double* r, int cells, double thr, int* list, int
 hipError_t launch_gather_cells(int scatter, const float* src, float* dst, const int* list, int count, int n3,
                                void* stream);
 
+// Library-owned device scratch of fks_collide_noalloc (one array per device, fixed size):
+// its device address on the current device (looked up once per device, then cached).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 // f = (f + g) / 2 elementwise over n values
 hipError_t launch_average(int dtype_is_f32, void* f, const void* g, int64_t n, void* stream);
 
