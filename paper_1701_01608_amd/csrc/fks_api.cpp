@@ -1449,15 +1449,15 @@ fks_status fks_step_ex(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt,
     const bool last = st == n_steps - 1;
     s = check_hip(fks::launch_xport_advance(xs, x->n, x->L, dt, x->dx, stream), "transport advance");
     if (s != FKS_OK) return s;
-    if (o.d_cons) {
+    if (o.d_cons) {  // eq. DM_update from the masses before the shift
       a.q = nullptr;
       a.moments = nullptr;
       a.prim = last ? o.d_prim : nullptr;
-      s = check_hip(fks::launch_step_cell(f32, f, f_tmp, xs.dl, 1, 0, a, stream), "transport + DM update");
-    } else {
-      s = check_hip(fks::launch_roll(f32, f, f_tmp, xs.dl, x->n * x->n * x->n, x->nx, x->ny, x->nz, stream),
-                    "transport roll");
+      s = check_hip(fks::launch_step_cell(f32, f, f_tmp, xs.dl, 1, 0, a, stream), "DM update");
+      if (s != FKS_OK) return s;
     }
+    s = check_hip(fks::launch_roll(f32, f, f_tmp, xs.dl, x->n * x->n * x->n, x->nx, x->ny, x->nz, stream),
+                  "transport roll");
     if (s != FKS_OK) return s;
     double* mom = nullptr;
     if (last) mom = o.d_moments ? o.d_moments : (o.d_prim && !o.d_cons ? o.d_prim : nullptr);

@@ -122,7 +122,9 @@ struct StepCellArgs {
   void* q;           // BGK: nu (E - f*) out, or null
   double* moments;   // direct moments of the output masses, or null
 };
-// mode 0: shift only; 1: BGK Euler; 2: BGK exact relaxation (modes 1, 2 need dm)
+// dm = 1 (required): eq. DM_update of the conservative variables from fin and this step's
+// shifts; mode 0: nothing more (the shift is launch_roll); 1: BGK Euler and 2: BGK exact
+// relaxation of the shifted masses into fout
 hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int dm, int mode,
                             const StepCellArgs& a, void* stream);
 hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream);

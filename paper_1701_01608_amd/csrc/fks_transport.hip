@@ -7,6 +7,8 @@
 //   t = s + v*dt;  delta = floor((t + dx/2) / dx);  s = t - delta*dx;  o += delta.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fks_internal.hpp"
 
 namespace fks {
@@ -39,6 +41,17 @@ __global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int n, doubl
   }
 }
 
+// (c - d) mod m for a shift d of at most one box length, without a division; larger shifts
+// take the remainder
+__device__ __forceinline__ int wrap_sub(int c, int d, int m) {
+  int s = c - d;
+  if (s < 0 || s >= m) {
+    s += (s < 0) ? m : -m;
+    if (s < 0 || s >= m) s = ((s % m) + m) % m;
+  }
+  return s;
+}
+
 // f_out[cell][k] = f_in[(cell - delta_k) mod box][k]; one thread per (cell, velocity),
 // consecutive threads on consecutive velocities of one destination cell.  The grid holds
 // blocks_per_cell blocks for each of a bounded number of cells and strides over the rest
@@ -50,38 +63,37 @@ __global__ __launch_bounds__(256) void k_roll(const T* __restrict__ fin, T* __re
   const int k = (blockIdx.x % blocks_per_cell) * blockDim.x + threadIdx.x;
   if (k >= nv) return;
   const int dx = dl[3 * k + 0], dy = dl[3 * k + 1], dz = dl[3 * k + 2];
-  const int64_t cells = int64_t(nx) * ny * nz;
-  const int64_t stride = gridDim.x / blocks_per_cell;
-  for (int64_t cell = blockIdx.x / blocks_per_cell; cell < cells; cell += stride) {
-    const int cx = int(cell / (int64_t(ny) * nz)), cy = int((cell / nz) % ny), cz = int(cell % nz);
-    int sx = (cx - dx) % nx;
-    int sy = (cy - dy) % ny;
-    int sz = (cz - dz) % nz;
-    sx += (sx < 0) ? nx : 0;
-    sy += (sy < 0) ? ny : 0;
-    sz += (sz < 0) ? nz : 0;
-    const size_t src = (size_t(sx) * ny + sy) * nz + sz;
-    fout[size_t(cell) * nv + k] = fin[src * nv + k];
+  // boxes hold at most 2^24 cells: 32-bit cell indices
+  const int cells = nx * ny * nz, nyz = ny * nz;
+  const int stride = int(gridDim.x) / blocks_per_cell;
+  for (int cell = int(blockIdx.x) / blocks_per_cell; cell < cells; cell += stride) {
+    const int cx = cell / nyz, cyz = cell - cx * nyz, cy = cyz / nz, cz = cyz - cy * nz;
+    const int src = (wrap_sub(cx, dx, nx) * ny + wrap_sub(cy, dy, ny)) * nz + wrap_sub(cz, dz, nz);
+    fout[size_t(cell) * nv + k] = fin[size_t(src) * nv + k];
   }
 }
 
 // ------------------------------------------------------------------------------------
-// Per-cell transport with the macroscopic variables (Section 3 eq. DM_update, Section 4.1
-// sequential algorithm) and, optionally, the BGK relaxation (Section 2.2.1).
-//
-// One workgroup owns one destination cell j at a time (grid-stride over the cells):
-//   1. DM_update: for every velocity k that moved this step (delta_k != 0) the sister
-//      particle from cell j - delta_k replaces the particle that left, so
-//      U_j += sum_k (f[j - delta_k][k] - f[j][k]) phi(v_k) dv^3 (FP64, fixed summation
-//      order: bitwise reproducible); ToPrimitive gives (rho, u, T) from U_j.
-//   2. the shifted masses f*[j][k] = f[j - delta_k][k] are written, or, with BGK, relaxed
-//      at frozen U_j towards E_jk = M_jk (1 + lambda . phi(v_k)), the sampled Maxwellian
-//      M = rho (2 pi T)^{-3/2} exp(-|v - u|^2 / 2T) times the affine factor in the
-//      invariants that makes the discrete moments of E exactly U_j (so the relaxation
-//      conserves what DM_update assumes it conserves): Euler f* + dt nu (E - f*) (eq.
-//      disc_relax) or exact E + (f* - E) exp(-nu dt).  M is separable: one Gaussian factor
-//      per axis in LDS, and every moment of M against two invariants is a product of three
-//      1-D moments, which gives the 5 x 5 system for lambda per cell.
+// The macroscopic variables of the FKS step (Section 3 eq. DM_update, Section 4.1
+// sequential algorithm) and the BGK relaxation (Section 2.2.1), in three kernels:
+//   k_dm_update   one workgroup per cell j: for every velocity k that moved this step
+//                 (delta_k != 0) the sister particle from cell j - delta_k replaces the one
+//                 that left, U_j += sum_k (f[j - delta_k][k] - f[j][k]) phi(v_k) dv^3 (FP64,
+//                 fixed summation order: bitwise reproducible); ToPrimitive (rho, u, T).
+//   k_bgk_setup   one thread per cell: E_jk = M_jk (1 + lambda . phi(v_k)), the sampled
+//                 Maxwellian M = rho (2 pi T)^{-3/2} exp(-|v - u|^2 / 2T) times the affine
+//                 factor in the invariants that gives E exactly the discrete moments U_j (so
+//                 the relaxation conserves what DM_update assumes it conserves).  M is
+//                 separable (one Gaussian factor per axis) and every grid moment of M against
+//                 two invariants is a product of three 1-D moments: the 5 x 5 system for
+//                 lambda is assembled in closed form and solved by Cholesky (it is symmetric
+//                 positive definite).  The factors and constants are parked at the start of
+//                 the cell's output block, which only this cell's relaxation workgroup writes.
+//   k_bgk_relax   one workgroup per cell: reads its parked constants, then streams
+//                 f*[j][k] = f[j - delta_k][k] relaxed at frozen U_j: Euler f* + dt nu (E - f*)
+//                 (eq. disc_relax) or exact E + (f* - E) exp(-nu dt).
+// Splitting keeps each streaming kernel's registers small (the per-cell setup in FP64,
+// inlined into the streaming loop, held 150+ registers and left 2-3 waves per SIMD).
 __device__ __forceinline__ void block_sum5(double (&v)[5], double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = 0; i < 5; ++i) {
@@ -108,162 +120,239 @@ __device__ __forceinline__ void to_primitive(const double* U, double* W) {
   W[4] = (2.0 / 3.0) * (U[4] / rho - 0.5 * (ux * ux + uy * uy + uz * uz));
 }
 
-template <typename T, bool DM, int MODE>
-__global__ __launch_bounds__(256) void k_step_cell(const T* __restrict__ fin, T* __restrict__ fout,
-                                                   const int32_t* __restrict__ dl, StepCellArgs a) {
+
+// velocities per thread and pass of the streaming loops: their loads are all issued
+// before any is used, so that a wave keeps several gathers in flight; the pass loop itself
+// is not unrolled
+constexpr int kStreamUnroll = 8;
+constexpr int kStreamThreads = 256;
+
+// source element of velocity k for destination cell (cx, cy, cz)
+__device__ __forceinline__ size_t source_index(int cx, int cy, int cz, int dx, int dy, int dz, int nx, int ny,
+                                               int nz, int nv, int k) {
+  return ((size_t(wrap_sub(cx, dx, nx)) * ny + wrap_sub(cy, dy, ny)) * nz + wrap_sub(cz, dz, nz)) * size_t(nv) +
+         size_t(k);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_dm_update(const T* __restrict__ fin, const int32_t* __restrict__ dl,
+                                                   StepCellArgs a) {
 #pragma clang fp contract(off)
-  constexpr int kMaxN = 64;
+  constexpr int nv = N * N * N, UNR = kStreamUnroll, NTH = kStreamThreads;
   __shared__ double red[5 * 16];
-  __shared__ double sW[8];
-  __shared__ double gd[3][kMaxN];
-  __shared__ double sA[3][5];
-  __shared__ double sLam[5];
-  const int n = a.n, nv = n * n * n;
-  const double dv = 2.0 * a.L / n, w3 = dv * dv * dv;
+  const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
   const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
   const int tid = threadIdx.x;
-  T* q = static_cast<T*>(a.q);
   for (int64_t cell = blockIdx.x; cell < cells; cell += gridDim.x) {
     const int cx = int(cell / (int64_t(a.ny) * a.nz)), cy = int((cell / a.nz) % a.ny), cz = int(cell % a.nz);
-    const T* fdst_old = fin + size_t(cell) * nv;
-    auto source = [&](int k) {
-      int sx = (cx - dl[3 * k + 0]) % a.nx, sy = (cy - dl[3 * k + 1]) % a.ny, sz = (cz - dl[3 * k + 2]) % a.nz;
-      sx += (sx < 0) ? a.nx : 0;
-      sy += (sy < 0) ? a.ny : 0;
-      sz += (sz < 0) ? a.nz : 0;
-      return ((size_t(sx) * a.ny + sy) * a.nz + sz) * size_t(nv) + size_t(k);
-    };
-    if constexpr (DM) {
-      double acc[5] = {0, 0, 0, 0, 0};
-      for (int k = tid; k < nv; k += blockDim.x) {
-        if ((dl[3 * k + 0] | dl[3 * k + 1] | dl[3 * k + 2]) == 0) continue;
-        const double diff = double(fin[source(k)]) - double(fdst_old[k]);
-        const double vx = -a.L + double(k / (n * n)) * dv, vy = -a.L + double((k / n) % n) * dv,
-                     vz = -a.L + double(k % n) * dv;
+    const T* fold = fin + size_t(cell) * nv;
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int k0 = 0; k0 < nv; k0 += NTH * UNR) {
+      T va[UNR], vb[UNR];
+      bool mv[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * NTH + tid;
+        mv[u] = false;
+        va[u] = vb[u] = T(0);
+        if (k < nv) {
+          const int dx = dl[3 * k + 0], dy = dl[3 * k + 1], dz = dl[3 * k + 2];
+          mv[u] = (dx | dy | dz) != 0;
+          if (mv[u]) {
+            va[u] = fin[source_index(cx, cy, cz, dx, dy, dz, a.nx, a.ny, a.nz, nv, k)];
+            vb[u] = fold[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (!mv[u]) continue;
+        const int k = k0 + u * NTH + tid;
+        const double diff = double(va[u]) - double(vb[u]);
+        const double vx = -a.L + double(k / (N * N)) * dv, vy = -a.L + double((k / N) % N) * dv,
+                     vz = -a.L + double(k % N) * dv;
         acc[0] += diff;
         acc[1] += diff * vx;
         acc[2] += diff * vy;
         acc[3] += diff * vz;
         acc[4] += diff * (0.5 * (vx * vx + vy * vy + vz * vz));
       }
-      block_sum5(acc, red);
-      if (tid == 0) {
-        double U[5], W[5];
-        for (int i = 0; i < 5; ++i) {
-          U[i] = a.cons[cell * 5 + i] + acc[i] * w3;
-          a.cons[cell * 5 + i] = U[i];
-        }
+    }
+    block_sum5(acc, red);
+    if (tid == 0) {
+      double U[5], W[5];
+      for (int i = 0; i < 5; ++i) {
+        U[i] = a.cons[cell * 5 + i] + acc[i] * w3;
+        a.cons[cell * 5 + i] = U[i];
+      }
+      if (a.prim) {
         to_primitive(U, W);
-        if (a.prim)
-          for (int i = 0; i < 5; ++i) a.prim[cell * 5 + i] = W[i];
-        for (int i = 0; i < 5; ++i) sW[i] = W[i];
+        for (int i = 0; i < 5; ++i) a.prim[cell * 5 + i] = W[i];
       }
-      __syncthreads();
     }
-    if constexpr (MODE != 0) {
-      // the cell's Maxwellian: one Gaussian factor per axis
-      const double T0 = sW[4];
-      if (tid < 3 * n) {
-        const int ax = tid / n, i = tid % n;
-        const double d = -a.L + double(i) * dv - sW[1 + ax];
-        gd[ax][i] = exp(-d * d / (2.0 * T0));
-      }
-      __syncthreads();
-      // 1-D moments A[ax][p] = sum_i g_ax(v_i) v_i^p, p <= 4: every grid moment of the
-      // separable M against a product of two invariants is a product of three of them
-      if (tid < 15) {
-        const int ax = tid / 5, pw = tid % 5;
-        double acc = 0.0;
-        for (int i = 0; i < n; ++i) {
-          const double v = -a.L + double(i) * dv;
-          double m = gd[ax][i];
-          for (int e = 0; e < pw; ++e) m *= v;
-          acc += m;
-        }
-        sA[ax][pw] = acc;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        const double rho = sW[0];
-        const double nu = a.nu_density ? a.nu * rho : a.nu;
-        const double pref = rho * pow(2.0 * 3.14159265358979323846 * T0, -1.5);
-        // invariants as polynomials: (coefficient, exponents of v_x, v_y, v_z)
-        struct Term {
-          double c;
-          int p[3];
-        };
-        const Term terms[7] = {{1.0, {0, 0, 0}}, {1.0, {1, 0, 0}}, {1.0, {0, 1, 0}}, {1.0, {0, 0, 1}},
-                               {0.5, {2, 0, 0}}, {0.5, {0, 2, 0}}, {0.5, {0, 0, 2}}};
-        const int first[6] = {0, 1, 2, 3, 4, 7};  // phi_i = terms[first[i] .. first[i+1])
-        auto mono = [&](const int* p, const int* q) {
-          return sA[0][p[0] + q[0]] * sA[1][p[1] + q[1]] * sA[2][p[2] + q[2]];
-        };
-        const int zero[3] = {0, 0, 0};
-        // G lambda = U / (pref dv^3) - m:  G_ij = sum_k g phi_i phi_j,  m_i = sum_k g phi_i
-        double G[5][6];
-        for (int i = 0; i < 5; ++i) {
-          for (int j = 0; j < 5; ++j) {
-            double acc = 0.0;
-            for (int u = first[i]; u < first[i + 1]; ++u)
-              for (int v = first[j]; v < first[j + 1]; ++v) acc += terms[u].c * terms[v].c * mono(terms[u].p, terms[v].p);
-            G[i][j] = acc;
-          }
-          double m = 0.0;
-          for (int u = first[i]; u < first[i + 1]; ++u) m += terms[u].c * mono(terms[u].p, zero);
-          G[i][5] = a.cons[cell * 5 + i] / (pref * w3) - m;
-        }
-        for (int c = 0; c < 5; ++c) {  // Gauss-Jordan, partial pivoting
-          int piv = c;
-          for (int r = c + 1; r < 5; ++r)
-            if (fabs(G[r][c]) > fabs(G[piv][c])) piv = r;
-          if (piv != c)
-            for (int k = 0; k < 6; ++k) {
-              const double t = G[c][k];
-              G[c][k] = G[piv][k];
-              G[piv][k] = t;
-            }
-          const double inv = 1.0 / G[c][c];
-          for (int k = c; k < 6; ++k) G[c][k] *= inv;
-          for (int r = 0; r < 5; ++r)
-            if (r != c) {
-              const double fct = G[r][c];
-              for (int k = c; k < 6; ++k) G[r][k] -= fct * G[c][k];
-            }
-        }
-        for (int i = 0; i < 5; ++i) sLam[i] = G[i][5];
-        sW[5] = pref;
-        sW[6] = nu;
-        sW[7] = MODE == 2 ? exp(-nu * a.dt) : nu * a.dt;
-      }
-      __syncthreads();
+  }
+}
+
+// parked per-cell constants of the relaxation, in doubles at the start of the cell's
+// output block: [0] pref, [1] nu, [2] rate (exp(-nu dt) or nu dt), [3..7] lambda,
+// [8 .. 8 + 3N) the Gaussian factors of the three axes
+template <int N>
+struct BgkPark {
+  static constexpr int kDoubles = 8 + 3 * N;
+};
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(256) void k_bgk_setup(T* __restrict__ fout, StepCellArgs a) {
+  constexpr int nv = N * N * N;
+  static_assert(size_t(BgkPark<N>::kDoubles) * sizeof(double) <= size_t(nv) * sizeof(T), "cell too small to park");
+  const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= cells) return;
+  const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
+  double U[5], W[5];
+  for (int i = 0; i < 5; ++i) U[i] = a.cons[cell * 5 + i];
+  to_primitive(U, W);
+  double* park = reinterpret_cast<double*>(fout + size_t(cell) * nv);
+  // Gaussian factors and their 1-D moments A[ax][p] = sum_i g_ax(v_i) v_i^p, p <= 4
+  double A[3][5];
+  for (int ax = 0; ax < 3; ++ax) {
+    for (int p = 0; p < 5; ++p) A[ax][p] = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double v = -a.L + double(i) * dv;
+      const double d = v - W[1 + ax];
+      const double g = exp(-d * d / (2.0 * W[4]));
+      park[8 + ax * N + i] = g;
+      A[ax][0] += g;
+      A[ax][1] += g * v;
+      A[ax][2] += g * v * v;
+      A[ax][3] += g * v * v * v;
+      A[ax][4] += g * v * v * v * v;
     }
+  }
+  auto m3 = [&](int px, int py, int pz) { return A[0][px] * A[1][py] * A[2][pz]; };
+  // G_ij = sum_k g phi_i phi_j over phi = (1, v_x, v_y, v_z, |v|^2/2); m_i = G_0i
+  double G[5][5];
+  G[0][0] = m3(0, 0, 0);
+  G[0][1] = m3(1, 0, 0);
+  G[0][2] = m3(0, 1, 0);
+  G[0][3] = m3(0, 0, 1);
+  G[0][4] = 0.5 * (m3(2, 0, 0) + m3(0, 2, 0) + m3(0, 0, 2));
+  G[1][1] = m3(2, 0, 0);
+  G[1][2] = m3(1, 1, 0);
+  G[1][3] = m3(1, 0, 1);
+  G[1][4] = 0.5 * (m3(3, 0, 0) + m3(1, 2, 0) + m3(1, 0, 2));
+  G[2][2] = m3(0, 2, 0);
+  G[2][3] = m3(0, 1, 1);
+  G[2][4] = 0.5 * (m3(2, 1, 0) + m3(0, 3, 0) + m3(0, 1, 2));
+  G[3][3] = m3(0, 0, 2);
+  G[3][4] = 0.5 * (m3(2, 0, 1) + m3(0, 2, 1) + m3(0, 0, 3));
+  G[4][4] = 0.25 * (m3(4, 0, 0) + m3(0, 4, 0) + m3(0, 0, 4)) + 0.5 * (m3(2, 2, 0) + m3(2, 0, 2) + m3(0, 2, 2));
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < i; ++j) G[i][j] = G[j][i];
+  const double tt = 2.0 * 3.14159265358979323846 * W[4];
+  const double pref = W[0] / (tt * sqrt(tt));
+  double lam[5];
+  for (int i = 0; i < 5; ++i) lam[i] = U[i] / (pref * w3) - G[0][i];
+  // G = C C^T (C lower, in place), then C y = b, C^T lambda = y
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    double d = G[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
+    G[j][j] = sqrt(d);
+    const double inv = 1.0 / G[j][j];
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      double v = G[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= G[i][k] * G[j][k];
+      G[i][j] = v * inv;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double v = lam[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= G[i][k] * lam[k];
+    lam[i] = v / G[i][i];
+  }
+#pragma unroll
+  for (int i = 4; i >= 0; --i) {
+    double v = lam[i];
+#pragma unroll
+    for (int k = i + 1; k < 5; ++k) v -= G[k][i] * lam[k];
+    lam[i] = v / G[i][i];
+  }
+  const double nu = a.nu_density ? a.nu * W[0] : a.nu;
+  park[0] = pref;
+  park[1] = nu;
+  park[2] = MODE == 2 ? exp(-nu * a.dt) : nu * a.dt;
+  for (int i = 0; i < 5; ++i) park[3 + i] = lam[i];
+}
+
+// EXTRAS: the collision operator and/or the direct moments are also written (last step);
+// without them the streaming loop holds no FP64 accumulators
+template <typename T, int N, int MODE, bool EXTRAS>
+__global__ __launch_bounds__(256) void k_bgk_relax(const T* __restrict__ fin, T* __restrict__ fout,
+                                                   const int32_t* __restrict__ dl, StepCellArgs a) {
+#pragma clang fp contract(off)
+  constexpr int nv = N * N * N, UNR = kStreamUnroll, NTH = kStreamThreads, NP = BgkPark<N>::kDoubles;
+  // the Maxwellian and the relaxation are evaluated in the storage precision (FP32 cells:
+  // a few FP32 roundings, far below the rounding of the stored result's neighbours; FP64:
+  // FP64); the optional moments are FP64 sums
+  using R = T;
+  __shared__ double red[5 * 16];
+  __shared__ R sp[NP];
+  const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
+  const R Lr = R(a.L), dvr = R(dv);
+  const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
+  const int tid = threadIdx.x;
+  T* q = static_cast<T*>(a.q);
+  for (int64_t cell = blockIdx.x; cell < cells; cell += gridDim.x) {
+    const int cx = int(cell / (int64_t(a.ny) * a.nz)), cy = int((cell / a.nz) % a.ny), cz = int(cell % a.nz);
+    T* fo = fout + size_t(cell) * nv;
+    if (tid < NP) sp[tid] = R(reinterpret_cast<const double*>(fo)[tid]);
+    __syncthreads();  // the parked constants are read before the cell's block is overwritten
+    const R pref = sp[0], nu_c = sp[1], rate = sp[2];
     double mom[5] = {0, 0, 0, 0, 0};
-    const double pref = MODE != 0 ? sW[5] : 0.0, nu_c = MODE != 0 ? sW[6] : 0.0, rate = MODE != 0 ? sW[7] : 0.0;
-    for (int k = tid; k < nv; k += blockDim.x) {
-      const T fs = fin[source(k)];
-      T out = fs;
-      const int ix = k / (n * n), iy = (k / n) % n, iz = k % n;
-      if constexpr (MODE != 0) {
-        const double vx = -a.L + double(ix) * dv, vy = -a.L + double(iy) * dv, vz = -a.L + double(iz) * dv;
-        const double corr = 1.0 + sLam[0] + sLam[1] * vx + sLam[2] * vy + sLam[3] * vz +
-                            sLam[4] * (0.5 * (vx * vx + vy * vy + vz * vz));
-        const double E = pref * gd[0][ix] * gd[1][iy] * gd[2][iz] * corr;
-        const double x = double(fs);
-        if (q) q[size_t(cell) * nv + k] = T(nu_c * (E - x));
-        out = T(MODE == 2 ? E + (x - E) * rate : x + rate * (E - x));
+#pragma unroll 1
+    for (int k0 = 0; k0 < nv; k0 += NTH * UNR) {
+      T vs[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * NTH + tid;
+        vs[u] = T(0);
+        if (k < nv)
+          vs[u] = fin[source_index(cx, cy, cz, dl[3 * k + 0], dl[3 * k + 1], dl[3 * k + 2], a.nx, a.ny, a.nz, nv, k)];
       }
-      fout[size_t(cell) * nv + k] = out;
-      if (a.moments) {
-        const double d = double(out);
-        const double vx = -a.L + double(ix) * dv, vy = -a.L + double(iy) * dv, vz = -a.L + double(iz) * dv;
-        mom[0] += d;
-        mom[1] += d * vx;
-        mom[2] += d * vy;
-        mom[3] += d * vz;
-        mom[4] += d * (0.5 * (vx * vx + vy * vy + vz * vz));
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * NTH + tid;
+        if (k >= nv) continue;
+        const int ix = k / (N * N), iy = (k / N) % N, iz = k % N;
+        const R vx = -Lr + R(ix) * dvr, vy = -Lr + R(iy) * dvr, vz = -Lr + R(iz) * dvr;
+        const R corr = R(1) + sp[3] + sp[4] * vx + sp[5] * vy + sp[6] * vz +
+                       sp[7] * (R(0.5) * (vx * vx + vy * vy + vz * vz));
+        const R E = pref * sp[8 + ix] * sp[8 + N + iy] * sp[8 + 2 * N + iz] * corr;
+        const R x = vs[u];
+        const T out = MODE == 2 ? E + (x - E) * rate : x + rate * (E - x);
+        fo[k] = out;
+        if constexpr (EXTRAS) {
+          if (q) q[size_t(cell) * nv + k] = nu_c * (E - x);
+        }
+        if (EXTRAS && a.moments) {
+          const double d = double(out);
+          const double wx = -a.L + double(ix) * dv, wy = -a.L + double(iy) * dv, wz = -a.L + double(iz) * dv;
+          mom[0] += d;
+          mom[1] += d * wx;
+          mom[2] += d * wy;
+          mom[3] += d * wz;
+          mom[4] += d * (0.5 * (wx * wx + wy * wy + wz * wz));
+        }
       }
     }
-    if (a.moments) {
+    if (EXTRAS && a.moments) {
       block_sum5(mom, red);
       if (tid == 0)
         for (int i = 0; i < 5; ++i) a.moments[cell * 5 + i] = mom[i] * w3;
@@ -325,34 +414,45 @@ hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int3
 
 hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int dm, int mode,
                             const StepCellArgs& a, void* stream) {
-  if (a.n > 64 || 3 * a.n > 256) return hipErrorInvalidValue;
   const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
   const dim3 grid(unsigned(cells < (int64_t(1) << 20) ? cells : (int64_t(1) << 20)));
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // the relaxation needs the DM-updated U; without a relaxation this is the DM update only
+  if (!dm) return hipErrorInvalidValue;
+  auto go = [&](auto tag, auto nc) -> hipError_t {
+    using T = decltype(tag);
+    constexpr int NN = decltype(nc)::value;
+    const T* fi = static_cast<const T*>(fin);
+    T* fo = static_cast<T*>(fout);
+    hipLaunchKernelGGL((k_dm_update<T, NN>), grid, dim3(kStreamThreads), 0, st, fi, dl, a);
+    if (mode == 0) return hipGetLastError();
+    const dim3 sgrid(unsigned((cells + 255) / 256));
+    const bool extras = a.q || a.moments;
+    if (mode == 1) {
+      hipLaunchKernelGGL((k_bgk_setup<T, NN, 1>), sgrid, dim3(256), 0, st, fo, a);
+      if (extras) hipLaunchKernelGGL((k_bgk_relax<T, NN, 1, true>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
+      else hipLaunchKernelGGL((k_bgk_relax<T, NN, 1, false>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
+    } else {
+      hipLaunchKernelGGL((k_bgk_setup<T, NN, 2>), sgrid, dim3(256), 0, st, fo, a);
+      if (extras) hipLaunchKernelGGL((k_bgk_relax<T, NN, 2, true>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
+      else hipLaunchKernelGGL((k_bgk_relax<T, NN, 2, false>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
+    }
+    return hipGetLastError();
+  };
+  auto by_n = [&](auto tag) -> hipError_t {
+    switch (a.n) {
+      case 8: return go(tag, std::integral_constant<int, 8>{});
+      case 12: return go(tag, std::integral_constant<int, 12>{});
+      case 16: return go(tag, std::integral_constant<int, 16>{});
+      case 24: return go(tag, std::integral_constant<int, 24>{});
+      case 32: return go(tag, std::integral_constant<int, 32>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
   prof_mark(kProfRoll, true, st);
-#define FKS_STEP_CELL(T, D, M)                                                                               \
-  hipLaunchKernelGGL((k_step_cell<T, D, M>), grid, dim3(256), 0, st, static_cast<const T*>(fin), static_cast<T*>(fout), \
-                     dl, a)
-  if (dtype_is_f32) {
-    if (dm) {
-      if (mode == 0) FKS_STEP_CELL(float, true, 0);
-      else if (mode == 1) FKS_STEP_CELL(float, true, 1);
-      else FKS_STEP_CELL(float, true, 2);
-    } else {
-      FKS_STEP_CELL(float, false, 0);
-    }
-  } else {
-    if (dm) {
-      if (mode == 0) FKS_STEP_CELL(double, true, 0);
-      else if (mode == 1) FKS_STEP_CELL(double, true, 1);
-      else FKS_STEP_CELL(double, true, 2);
-    } else {
-      FKS_STEP_CELL(double, false, 0);
-    }
-  }
-#undef FKS_STEP_CELL
+  const hipError_t e = dtype_is_f32 ? by_n(float{}) : by_n(double{});
   prof_mark(kProfRoll, false, st);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream) {
