@@ -156,3 +156,25 @@ def test_bkw_input_profile_is_the_pinned_closed_form():
     V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
     for t in (5.5, 6.5):
         np.testing.assert_allclose(fks_inputs.bkw_initial(n, L, t), bkw.f_bkw(t, V), rtol=1e-14, atol=1e-17)
+
+
+@pytest.mark.slow
+def test_bkw_trajectory_converges_with_directions():
+    # the BKW relaxation run's Heun trajectory (Maxwell molecules, 8 radial nodes, dt = 0.01,
+    # 100 steps from t0 = 5.5) against the closed form at t0 + 1.  On the n = 16 grid (dv = 1) the
+    # error is set by the grid: 0.086, 0.081, 0.080 for M = 6, 16, 64 directions (measured);
+    # on n = 24 the grid error is smaller and the angular quadrature shows: M = 6 -> 16 cuts
+    # the error 0.028 -> 0.008 (O(A^-2) of the midpoint rule)
+    n, L, R, C = 24, 8.0, 6.0, 1 / (4 * np.pi)
+    from oracle.integrators import heun
+    v1 = fks_inputs.velocity_axis(n, L)
+    V = np.stack(np.meshgrid(v1, v1, v1, indexing="ij"), -1)
+    exact = bkw.f_bkw(6.5, V)
+    errs = []
+    for a1, a2 in ((2, 3), (4, 4)):
+        plan = make_plan(n, L, R, kernel=VHS, alpha=0.0, C=C, a1=a1, a2=a2, n_radial=8)
+        f = fks_inputs.bkw_initial(n, L, 5.5)
+        for _ in range(100):
+            f = heun(f, lambda g: collide_fast(g, plan), 0.01)
+        errs.append(np.linalg.norm(f - exact) / np.linalg.norm(exact))
+    assert errs[1] < 0.01 and errs[0] / errs[1] > 2.5, errs
