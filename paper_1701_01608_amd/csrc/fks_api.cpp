@@ -1297,7 +1297,8 @@ void fks_graph_destroy(fks_graph g) {
 fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t nz, double dx, fks_xport* out) {
   if (!out) return fail(FKS_E_ARG, "null out");
   *out = nullptr;
-  if (n < 2 || n > 64) return fail(FKS_E_ARG, "n out of range");
+  if (n != 8 && n != 12 && n != 16 && n != 24 && n != 32)
+    return fail(FKS_E_UNSUPPORTED, "transport velocity grids: n in {8, 12, 16, 24, 32}, got %d", n);
   if (nx < 1 || ny < 1 || nz < 1) return fail(FKS_E_ARG, "box sizes must be >= 1");
   if (int64_t(nx) * ny * nz > (int64_t(1) << 24)) return fail(FKS_E_ARG, "too many cells");
   if (!(L > 0.0) || !(dx > 0.0) || !std::isfinite(L) || !std::isfinite(dx))
@@ -1317,7 +1318,7 @@ fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t
 fks_status fks_xport_sizes(fks_xport x, size_t* state_bytes) {
   if (!x || !state_bytes) return fail(FKS_E_ARG, "null argument");
   const size_t nv = size_t(x->n) * x->n * x->n;
-  *state_bytes = round256(nv * 3 * 8) + round256(nv * 3 * 4) + round256(nv * 3 * 4);
+  *state_bytes = round256(nv * 3 * 8) + round256(nv * 3 * 4) + round256(nv * 3 * 4) + round256(size_t(x->n) * 3 * 4);
   return ok();
 }
 
@@ -1328,6 +1329,7 @@ static fks::XportState xport_state(fks_xport x) {
   st.s = reinterpret_cast<double*>(b);
   st.o = reinterpret_cast<int32_t*>(b + round256(nv * 3 * 8));
   st.dl = reinterpret_cast<int32_t*>(b + round256(nv * 3 * 8) + round256(nv * 3 * 4));
+  st.d1 = reinterpret_cast<int32_t*>(b + round256(nv * 3 * 8) + 2 * round256(nv * 3 * 4));
   return st;
 }
 
@@ -1339,7 +1341,7 @@ fks_status fks_xport_bind(fks_xport x, void* d_state, size_t state_bytes, void* 
   if (state_bytes < need) return fail(FKS_E_WORKSPACE, "state buffer %zu < %zu bytes", state_bytes, need);
   x->d_state = d_state;
   x->bound = true;
-  return check_hip(fks::launch_xport_reset(xport_state(x), x->n * x->n * x->n, stream), "transport reset") ==
+  return check_hip(fks::launch_xport_reset(xport_state(x), x->n, stream), "transport reset") ==
                  FKS_OK
              ? ok()
              : FKS_E_DEVICE;
@@ -1357,7 +1359,7 @@ fks_status fks_transport(fks_xport x, const void* f_in, void* f_out, int32_t dty
   const fks::XportState st = xport_state(x);
   fks_status s = check_hip(fks::launch_xport_advance(st, x->n, x->L, dt, x->dx, stream), "transport advance");
   if (s != FKS_OK) return s;
-  s = check_hip(fks::launch_roll(dtype == FKS_F32, f_in, f_out, st.dl, nv, x->nx, x->ny, x->nz, stream),
+  s = check_hip(fks::launch_roll(dtype == FKS_F32, f_in, f_out, st.d1, x->n, x->L, x->nx, x->ny, x->nz, stream),
                 "transport roll");
   if (s != FKS_OK) return s;
   return ok();
@@ -1437,7 +1439,7 @@ fks_status fks_step_ex(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt,
       if (s != FKS_OK) break;
       a.q = last ? o.q_last : nullptr;
       a.moments = last ? o.d_moments : nullptr;
-      s = check_hip(fks::launch_step_cell(f32, cur, nxt, xs.dl, 1, mode, a, stream), "BGK step");
+      s = check_hip(fks::launch_step_cell(f32, cur, nxt, xs.d1, mode, a, stream), "BGK step");
       std::swap(cur, nxt);
     }
     if (s == FKS_OK && cur != f)
@@ -1449,15 +1451,15 @@ fks_status fks_step_ex(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt,
     const bool last = st == n_steps - 1;
     s = check_hip(fks::launch_xport_advance(xs, x->n, x->L, dt, x->dx, stream), "transport advance");
     if (s != FKS_OK) return s;
-    if (o.d_cons) {  // eq. DM_update from the masses before the shift
+    if (o.d_cons) {  // the shift with eq. DM_update from the masses before it
       a.q = nullptr;
       a.moments = nullptr;
       a.prim = last ? o.d_prim : nullptr;
-      s = check_hip(fks::launch_step_cell(f32, f, f_tmp, xs.dl, 1, 0, a, stream), "DM update");
-      if (s != FKS_OK) return s;
+      s = check_hip(fks::launch_step_cell(f32, f, f_tmp, xs.d1, 0, a, stream), "transport with DM update");
+    } else {
+      s = check_hip(fks::launch_roll(f32, f, f_tmp, xs.d1, x->n, x->L, x->nx, x->ny, x->nz, stream),
+                    "transport roll");
     }
-    s = check_hip(fks::launch_roll(f32, f, f_tmp, xs.dl, x->n * x->n * x->n, x->nx, x->ny, x->nz, stream),
-                  "transport roll");
     if (s != FKS_OK) return s;
     double* mom = nullptr;
     if (last) mom = o.d_moments ? o.d_moments : (o.d_prim && !o.d_cons ? o.d_prim : nullptr);

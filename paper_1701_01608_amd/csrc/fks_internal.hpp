@@ -103,10 +103,12 @@ struct XportState {
   double* s;    // [nv][3] sub-cell offsets
   int32_t* o;   // [nv][3] cumulative integer shifts
   int32_t* dl;  // [nv][3] shift of the last step
+  int32_t* d1;  // [3][n] shift of the last step per axis and velocity index along that axis
 };
-hipError_t launch_xport_reset(const XportState& st, int nv, void* stream);
+hipError_t launch_xport_reset(const XportState& st, int n, void* stream);
 hipError_t launch_xport_advance(const XportState& st, int n, double L, double dt, double dx, void* stream);
-hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int nv, int nx,
+// f_out[j][k] = f_in[(j - delta_k) mod box][k] from the compact shift table
+hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int n, double L, int nx,
                        int ny, int nz, void* stream);
 
 // per-cell transport with eq. DM_update / ToPrimitive and optional BGK relaxation
@@ -122,10 +124,10 @@ struct StepCellArgs {
   void* q;           // BGK: nu (E - f*) out, or null
   double* moments;   // direct moments of the output masses, or null
 };
-// dm = 1 (required): eq. DM_update of the conservative variables from fin and this step's
-// shifts; mode 0: nothing more (the shift is launch_roll); 1: BGK Euler and 2: BGK exact
-// relaxation of the shifted masses into fout
-hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int dm, int mode,
+// The shift from fin to fout with eq. DM_update of the conservative variables a.cons from
+// fin and this step's shifts (required); mode 0: nothing more; 1: BGK Euler and 2: BGK exact
+// relaxation of the shifted masses at the updated U
+hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
                             const StepCellArgs& a, void* stream);
 hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream);
 hipError_t launch_copy(int dtype_is_f32, const void* src, void* dst, int64_t n, void* stream);

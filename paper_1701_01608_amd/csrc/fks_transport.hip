@@ -13,16 +13,22 @@
 
 namespace fks {
 
-__global__ void k_xport_reset(double* s, int32_t* o, int32_t* dl, int m) {
+__global__ void k_xport_reset(double* s, int32_t* o, int32_t* dl, int32_t* d1, int m, int m1) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     s[i] = 0.0;
     o[i] = 0;
     dl[i] = 0;
   }
+  if (i < m1) d1[i] = 0;
 }
 
-__global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int n, double L, double dt, double dx) {
+// The shift along axis a depends on the velocity's index along a only: every velocity
+// with the same component has the same offset history.  Besides the per-velocity state,
+// the velocities whose other two indices are zero write the step's shift of their axis
+// into the compact table d1[a][i] that the streaming kernels read.
+__global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int32_t* d1, int n, double L, double dt,
+                                double dx) {
 #pragma clang fp contract(off)
   const int nv = n * n * n;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,6 +44,7 @@ __global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int n, doubl
     s[3 * k + a] = t - d * dx;
     dl[3 * k + a] = int32_t(d);
     o[3 * k + a] += int32_t(d);
+    if (idx[(a + 1) % 3] == 0 && idx[(a + 2) % 3] == 0) d1[a * n + idx[a]] = int32_t(d);
   }
 }
 
@@ -52,48 +59,35 @@ __device__ __forceinline__ int wrap_sub(int c, int d, int m) {
   return s;
 }
 
-// f_out[cell][k] = f_in[(cell - delta_k) mod box][k]; one thread per (cell, velocity),
-// consecutive threads on consecutive velocities of one destination cell.  The grid holds
-// blocks_per_cell blocks for each of a bounded number of cells and strides over the rest
-// (the threads of one launch stay below 2^32 for any box).
-template <typename T>
-__global__ __launch_bounds__(256) void k_roll(const T* __restrict__ fin, T* __restrict__ fout,
-                                              const int32_t* __restrict__ dl, int nv, int nx, int ny, int nz,
-                                              int blocks_per_cell) {
-  const int k = (blockIdx.x % blocks_per_cell) * blockDim.x + threadIdx.x;
-  if (k >= nv) return;
-  const int dx = dl[3 * k + 0], dy = dl[3 * k + 1], dz = dl[3 * k + 2];
-  // boxes hold at most 2^24 cells: 32-bit cell indices
-  const int cells = nx * ny * nz, nyz = ny * nz;
-  const int stride = int(gridDim.x) / blocks_per_cell;
-  for (int cell = int(blockIdx.x) / blocks_per_cell; cell < cells; cell += stride) {
-    const int cx = cell / nyz, cyz = cell - cx * nyz, cy = cyz / nz, cz = cyz - cy * nz;
-    const int src = (wrap_sub(cx, dx, nx) * ny + wrap_sub(cy, dy, ny)) * nz + wrap_sub(cz, dz, nz);
-    fout[size_t(cell) * nv + k] = fin[size_t(src) * nv + k];
-  }
-}
-
 // ------------------------------------------------------------------------------------
-// The macroscopic variables of the FKS step (Section 3 eq. DM_update, Section 4.1
-// sequential algorithm) and the BGK relaxation (Section 2.2.1), in three kernels:
-//   k_dm_update   one workgroup per cell j: for every velocity k that moved this step
-//                 (delta_k != 0) the sister particle from cell j - delta_k replaces the one
-//                 that left, U_j += sum_k (f[j - delta_k][k] - f[j][k]) phi(v_k) dv^3 (FP64,
-//                 fixed summation order: bitwise reproducible); ToPrimitive (rho, u, T).
-//   k_bgk_setup   one thread per cell: E_jk = M_jk (1 + lambda . phi(v_k)), the sampled
-//                 Maxwellian M = rho (2 pi T)^{-3/2} exp(-|v - u|^2 / 2T) times the affine
-//                 factor in the invariants that gives E exactly the discrete moments U_j (so
-//                 the relaxation conserves what DM_update assumes it conserves).  M is
-//                 separable (one Gaussian factor per axis) and every grid moment of M against
-//                 two invariants is a product of three 1-D moments: the 5 x 5 system for
-//                 lambda is assembled in closed form and solved by Cholesky (it is symmetric
-//                 positive definite).  The factors and constants are parked at the start of
-//                 the cell's output block, which only this cell's relaxation workgroup writes.
-//   k_bgk_relax   one workgroup per cell: reads its parked constants, then streams
-//                 f*[j][k] = f[j - delta_k][k] relaxed at frozen U_j: Euler f* + dt nu (E - f*)
-//                 (eq. disc_relax) or exact E + (f* - E) exp(-nu dt).
-// Splitting keeps each streaming kernel's registers small (the per-cell setup in FP64,
-// inlined into the streaming loop, held 150+ registers and left 2-3 waves per SIMD).
+// One transport step per cell, with the macroscopic variables of the FKS step (Section 3
+// eq. DM_update, Section 4.1 sequential algorithm) and the BGK relaxation (Section 2.2.1),
+// in one kernel: one workgroup per destination cell j, streaming the cell's shifted
+// masses f*[j][k] = f[j - delta_k][k] in batches (a second time for the relaxation, after
+// the per-cell setup, mostly from L2).
+//   MODE 3  shift only: f_out = f*.
+//   MODE 0  shift and eq. DM_update: for every velocity k that moved this step
+//           (delta_k != 0) the sister particle from cell j - delta_k replaces the one that
+//           left, U_j += sum_k (f[j - delta_k][k] - f[j][k]) phi(v_k) dv^3 (FP64, fixed
+//           summation order: bitwise reproducible); ToPrimitive (rho, u, T) when asked.
+//   MODE 1  eq. DM_update, then the Euler relaxation f* + dt nu (E - f*) (eq. disc_relax),
+//   MODE 2  or the exact one E + (f* - E) exp(-nu dt), at the frozen updated U_j.
+// E_jk = M_jk (1 + lambda . phi(v_k)): the sampled Maxwellian M = rho (2 pi T)^{-3/2}
+// exp(-|v - u|^2 / 2T) of the updated U_j times the affine factor in the invariants that
+// gives E exactly the discrete moments U_j, so the relaxation conserves what DM_update
+// assumes it conserves.  M is separable (one Gaussian factor per axis) and every grid
+// moment of M against two invariants is a product of three 1-D moments: the 5 x 5 system
+// for lambda is assembled in closed form and solved by Cholesky (it is symmetric positive
+// definite).  Its setup runs once per cell between the two passes, each step spread over
+// threads through LDS.
+//
+// The shift of axis a depends on the velocity index along a only (the compact table d1),
+// so the source cell of velocity k is (sx[ix], sy[iy], sz[iz]) from three per-cell
+// tables.  Consecutive lanes take consecutive velocities of the destination cell, so
+// every load reads runs of consecutive values of one source cell and every store is
+// contiguous.  Workgroups are dealt to the 8 XCDs round-robin; each XCD gets a contiguous
+// range of cells, so the z neighbours a cell reads from, and the own-cell values of the
+// moved velocities that a z neighbour reads as its shifted masses, meet in one L2.
 __device__ __forceinline__ void block_sum5(double (&v)[5], double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = 0; i < 5; ++i) {
@@ -120,244 +114,321 @@ __device__ __forceinline__ void to_primitive(const double* U, double* W) {
   W[4] = (2.0 / 3.0) * (U[4] / rho - 0.5 * (ux * ux + uy * uy + uz * uz));
 }
 
-
-// velocities per thread and pass of the streaming loops: their loads are all issued
-// before any is used, so that a wave keeps several gathers in flight; the pass loop itself
-// is not unrolled
-constexpr int kStreamUnroll = 8;
-constexpr int kStreamThreads = 256;
-
-// source element of velocity k for destination cell (cx, cy, cz)
-__device__ __forceinline__ size_t source_index(int cx, int cy, int cz, int dx, int dy, int dz, int nx, int ny,
-                                               int nz, int nv, int k) {
-  return ((size_t(wrap_sub(cx, dx, nx)) * ny + wrap_sub(cy, dy, ny)) * nz + wrap_sub(cz, dz, nz)) * size_t(nv) +
-         size_t(k);
-}
-
+// threads per cell: velocity k = u NTH + t of thread t (u < VPT), so lanes take
+// consecutive velocities.  The workgroup is either m whole (v_y, v_z) planes (H = 1:
+// m N^2 threads, m | N, a multiple of 64), where a thread's y and z indices are fixed, or
+// half a plane (H = 2: N^2 / 2 threads, n = 32), where its y index alternates between two
+// values with the parity of u; ix = (u / H) m + t / N^2.  Half planes at n = 32 keep two
+// workgroups per CU, so one cell's setup overlaps another cell's streaming.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_dm_update(const T* __restrict__ fin, const int32_t* __restrict__ dl,
-                                                   StepCellArgs a) {
-#pragma clang fp contract(off)
-  constexpr int nv = N * N * N, UNR = kStreamUnroll, NTH = kStreamThreads;
-  __shared__ double red[5 * 16];
-  const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
-  const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
-  const int tid = threadIdx.x;
-  for (int64_t cell = blockIdx.x; cell < cells; cell += gridDim.x) {
-    const int cx = int(cell / (int64_t(a.ny) * a.nz)), cy = int((cell / a.nz) % a.ny), cz = int(cell % a.nz);
-    const T* fold = fin + size_t(cell) * nv;
-    double acc[5] = {0, 0, 0, 0, 0};
-#pragma unroll 1
-    for (int k0 = 0; k0 < nv; k0 += NTH * UNR) {
-      T va[UNR], vb[UNR];
-      bool mv[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * NTH + tid;
-        mv[u] = false;
-        va[u] = vb[u] = T(0);
-        if (k < nv) {
-          const int dx = dl[3 * k + 0], dy = dl[3 * k + 1], dz = dl[3 * k + 2];
-          mv[u] = (dx | dy | dz) != 0;
-          if (mv[u]) {
-            va[u] = fin[source_index(cx, cy, cz, dx, dy, dz, a.nx, a.ny, a.nz, nv, k)];
-            vb[u] = fold[k];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        if (!mv[u]) continue;
-        const int k = k0 + u * NTH + tid;
-        const double diff = double(va[u]) - double(vb[u]);
-        const double vx = -a.L + double(k / (N * N)) * dv, vy = -a.L + double((k / N) % N) * dv,
-                     vz = -a.L + double(k % N) * dv;
-        acc[0] += diff;
-        acc[1] += diff * vx;
-        acc[2] += diff * vy;
-        acc[3] += diff * vz;
-        acc[4] += diff * (0.5 * (vx * vx + vy * vy + vz * vz));
-      }
-    }
-    block_sum5(acc, red);
-    if (tid == 0) {
-      double U[5], W[5];
-      for (int i = 0; i < 5; ++i) {
-        U[i] = a.cons[cell * 5 + i] + acc[i] * w3;
-        a.cons[cell * 5 + i] = U[i];
-      }
-      if (a.prim) {
-        to_primitive(U, W);
-        for (int i = 0; i < 5; ++i) a.prim[cell * 5 + i] = W[i];
-      }
-    }
+struct CellShape {
+  static constexpr int NV = N * N * N;
+  static constexpr int H = N >= 32 ? 2 : 1;
+  static constexpr int M = H == 2 ? 1 : ((N * N) % 64 == 0 ? (N * N >= 256 ? 1 : 256 / (N * N)) : 4);
+  static constexpr int NTH = M * N * N / H;
+  static constexpr int VPT = NV / NTH;
+  static constexpr int YH = N / H;   // y indices per half
+  // values per streaming batch: the largest divisor of VPT up to 16 (n = 32) or 8 (smaller
+  // workgroups, where more of them share a CU)
+  static constexpr int batch() {
+    for (int b = N >= 32 ? 16 : 8; b > 1; --b)
+      if (VPT % b == 0 && b % H == 0) return b;
+    return 1;
   }
-}
-
-// parked per-cell constants of the relaxation, in doubles at the start of the cell's
-// output block: [0] pref, [1] nu, [2] rate (exp(-nu dt) or nu dt), [3..7] lambda,
-// [8 .. 8 + 3N) the Gaussian factors of the three axes
-template <int N>
-struct BgkPark {
-  static constexpr int kDoubles = 8 + 3 * N;
+  static constexpr int B = batch();
+  // waves per SIMD the register allocation must allow: small cells are latency bound and
+  // need many workgroups per CU in flight
+  static constexpr int MIN_WAVES = N >= 32 ? 4 : 1;
+  static_assert(N % M == 0 && NTH % 64 == 0 && NTH <= 1024 && NV % NTH == 0, "workgroup shape");
 };
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) void k_bgk_setup(T* __restrict__ fout, StepCellArgs a) {
-  constexpr int nv = N * N * N;
-  static_assert(size_t(BgkPark<N>::kDoubles) * sizeof(double) <= size_t(nv) * sizeof(T), "cell too small to park");
-  const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
-  const int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (cell >= cells) return;
-  const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
-  double U[5], W[5];
-  for (int i = 0; i < 5; ++i) U[i] = a.cons[cell * 5 + i];
-  to_primitive(U, W);
-  double* park = reinterpret_cast<double*>(fout + size_t(cell) * nv);
-  // Gaussian factors and their 1-D moments A[ax][p] = sum_i g_ax(v_i) v_i^p, p <= 4
-  double A[3][5];
-  for (int ax = 0; ax < 3; ++ax) {
-    for (int p = 0; p < 5; ++p) A[ax][p] = 0.0;
-    for (int i = 0; i < N; ++i) {
-      const double v = -a.L + double(i) * dv;
-      const double d = v - W[1 + ax];
-      const double g = exp(-d * d / (2.0 * W[4]));
-      park[8 + ax * N + i] = g;
-      A[ax][0] += g;
-      A[ax][1] += g * v;
-      A[ax][2] += g * v * v;
-      A[ax][3] += g * v * v * v;
-      A[ax][4] += g * v * v * v * v;
-    }
-  }
+// Entry (i, j) of the Gram matrix G_ij = sum_k g(v_k) phi_i phi_j of the separable
+// Gaussian g over phi = (1, v_x, v_y, v_z, |v|^2/2), from the 1-D moments
+// A[ax][p] = sum_i g_ax(v_i) v_i^p (p <= 4): each grid moment of a monomial is a product of
+// three 1-D moments.  i <= j.
+__device__ __forceinline__ double gram_entry(int i, int j, const double (*A)[5]) {
   auto m3 = [&](int px, int py, int pz) { return A[0][px] * A[1][py] * A[2][pz]; };
-  // G_ij = sum_k g phi_i phi_j over phi = (1, v_x, v_y, v_z, |v|^2/2); m_i = G_0i
-  double G[5][5];
-  G[0][0] = m3(0, 0, 0);
-  G[0][1] = m3(1, 0, 0);
-  G[0][2] = m3(0, 1, 0);
-  G[0][3] = m3(0, 0, 1);
-  G[0][4] = 0.5 * (m3(2, 0, 0) + m3(0, 2, 0) + m3(0, 0, 2));
-  G[1][1] = m3(2, 0, 0);
-  G[1][2] = m3(1, 1, 0);
-  G[1][3] = m3(1, 0, 1);
-  G[1][4] = 0.5 * (m3(3, 0, 0) + m3(1, 2, 0) + m3(1, 0, 2));
-  G[2][2] = m3(0, 2, 0);
-  G[2][3] = m3(0, 1, 1);
-  G[2][4] = 0.5 * (m3(2, 1, 0) + m3(0, 3, 0) + m3(0, 1, 2));
-  G[3][3] = m3(0, 0, 2);
-  G[3][4] = 0.5 * (m3(2, 0, 1) + m3(0, 2, 1) + m3(0, 0, 3));
-  G[4][4] = 0.25 * (m3(4, 0, 0) + m3(0, 4, 0) + m3(0, 0, 4)) + 0.5 * (m3(2, 2, 0) + m3(2, 0, 2) + m3(0, 2, 2));
-  for (int i = 0; i < 5; ++i)
-    for (int j = 0; j < i; ++j) G[i][j] = G[j][i];
-  const double tt = 2.0 * 3.14159265358979323846 * W[4];
-  const double pref = W[0] / (tt * sqrt(tt));
-  double lam[5];
-  for (int i = 0; i < 5; ++i) lam[i] = U[i] / (pref * w3) - G[0][i];
-  // G = C C^T (C lower, in place), then C y = b, C^T lambda = y
+  switch (i * 5 + j) {
+    case 0: return m3(0, 0, 0);
+    case 1: return m3(1, 0, 0);
+    case 2: return m3(0, 1, 0);
+    case 3: return m3(0, 0, 1);
+    case 4: return 0.5 * (m3(2, 0, 0) + m3(0, 2, 0) + m3(0, 0, 2));
+    case 6: return m3(2, 0, 0);
+    case 7: return m3(1, 1, 0);
+    case 8: return m3(1, 0, 1);
+    case 9: return 0.5 * (m3(3, 0, 0) + m3(1, 2, 0) + m3(1, 0, 2));
+    case 12: return m3(0, 2, 0);
+    case 13: return m3(0, 1, 1);
+    case 14: return 0.5 * (m3(2, 1, 0) + m3(0, 3, 0) + m3(0, 1, 2));
+    case 18: return m3(0, 0, 2);
+    case 19: return 0.5 * (m3(2, 0, 1) + m3(0, 2, 1) + m3(0, 0, 3));
+    default:  // (4, 4)
+      return 0.25 * (m3(4, 0, 0) + m3(0, 4, 0) + m3(0, 0, 4)) + 0.5 * (m3(2, 2, 0) + m3(2, 0, 2) + m3(0, 2, 2));
+  }
+}
+
+// Solves G lambda = b for the symmetric positive definite 5 x 5 G (upper triangle given)
+// by Cholesky, G = C C^T: C y = b, C^T lambda = y.  One thread, unrolled (in registers).
+__device__ __forceinline__ void solve5(const double (*G)[5], double* b) {
+  double C[5][5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     double d = G[j][j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
-    G[j][j] = sqrt(d);
-    const double inv = 1.0 / G[j][j];
+    for (int k = 0; k < j; ++k) d -= C[j][k] * C[j][k];
+    C[j][j] = sqrt(d);
+    const double inv = 1.0 / C[j][j];
 #pragma unroll
     for (int i = j + 1; i < 5; ++i) {
-      double v = G[i][j];
+      double v = G[j][i];
 #pragma unroll
-      for (int k = 0; k < j; ++k) v -= G[i][k] * G[j][k];
-      G[i][j] = v * inv;
+      for (int k = 0; k < j; ++k) v -= C[i][k] * C[j][k];
+      C[i][j] = v * inv;
     }
   }
+  double y[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    double v = lam[i];
+    double v = b[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) v -= G[i][k] * lam[k];
-    lam[i] = v / G[i][i];
+    for (int k = 0; k < i; ++k) v -= C[i][k] * y[k];
+    y[i] = v / C[i][i];
   }
 #pragma unroll
   for (int i = 4; i >= 0; --i) {
-    double v = lam[i];
+    double v = y[i];
 #pragma unroll
-    for (int k = i + 1; k < 5; ++k) v -= G[k][i] * lam[k];
-    lam[i] = v / G[i][i];
+    for (int k = i + 1; k < 5; ++k) v -= C[k][i] * b[k];
+    b[i] = v / C[i][i];
   }
-  const double nu = a.nu_density ? a.nu * W[0] : a.nu;
-  park[0] = pref;
-  park[1] = nu;
-  park[2] = MODE == 2 ? exp(-nu * a.dt) : nu * a.dt;
-  for (int i = 0; i < 5; ++i) park[3 + i] = lam[i];
 }
 
-// EXTRAS: the collision operator and/or the direct moments are also written (last step);
-// without them the streaming loop holds no FP64 accumulators
+// EXTRAS (BGK modes): the collision operator nu (E - f*) and/or the direct moments of the
+// output are also written (last step); without them the streaming loop holds no FP64
+// accumulators
 template <typename T, int N, int MODE, bool EXTRAS>
-__global__ __launch_bounds__(256) void k_bgk_relax(const T* __restrict__ fin, T* __restrict__ fout,
-                                                   const int32_t* __restrict__ dl, StepCellArgs a) {
+__global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES)) void k_cell_step(const T* __restrict__ fin,
+                                                                    T* __restrict__ fout,
+                                                                    const int32_t* __restrict__ d1,
+                                                                    StepCellArgs a) {
 #pragma clang fp contract(off)
-  constexpr int nv = N * N * N, UNR = kStreamUnroll, NTH = kStreamThreads, NP = BgkPark<N>::kDoubles;
+  using CS = CellShape<T, N>;
+  constexpr int NV = CS::NV, NTH = CS::NTH, VPT = CS::VPT;
+  constexpr bool DM = MODE != 3, BGK = MODE == 1 || MODE == 2;
   // the Maxwellian and the relaxation are evaluated in the storage precision (FP32 cells:
   // a few FP32 roundings, far below the rounding of the stored result's neighbours; FP64:
-  // FP64); the optional moments are FP64 sums
+  // FP64); the sums of DM_update and the optional moments are FP64
   using R = T;
+  __shared__ int src_ax[3][N];   // wrapped source coordinate per axis index
   __shared__ double red[5 * 16];
-  __shared__ R sp[NP];
+  __shared__ double Ush[5], Wsh[5], par[8];
+  __shared__ double gpow[3][5][N];
+  __shared__ double Ash[3][5], Gsh[5][5];
+  __shared__ R gr[3 * N];
   const double dv = 2.0 * a.L / N, w3 = dv * dv * dv;
-  const R Lr = R(a.L), dvr = R(dv);
-  const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
+  const int cells = a.nx * a.ny * a.nz, nyz = a.ny * a.nz;
   const int tid = threadIdx.x;
   T* q = static_cast<T*>(a.q);
-  for (int64_t cell = blockIdx.x; cell < cells; cell += gridDim.x) {
-    const int cx = int(cell / (int64_t(a.ny) * a.nz)), cy = int((cell / a.nz) % a.ny), cz = int(cell % a.nz);
-    T* fo = fout + size_t(cell) * nv;
-    if (tid < NP) sp[tid] = R(reinterpret_cast<const double*>(fo)[tid]);
-    __syncthreads();  // the parked constants are read before the cell's block is overwritten
-    const R pref = sp[0], nu_c = sp[1], rate = sp[2];
-    double mom[5] = {0, 0, 0, 0, 0};
+  // rounds of gridDim.x cells; within a round XCD x (blockIdx % 8) takes a contiguous range
+  const int per_xcd = int(gridDim.x) >> 3;
+  const int slot = int(blockIdx.x & 7) * per_xcd + int(blockIdx.x >> 3);
+  for (int base = 0; base < cells; base += int(gridDim.x)) {
+    const int cell = base + slot;
+    if (cell >= cells) break;  // uniform over the workgroup
+    const int cx = cell / nyz, cyz = cell - cx * nyz, cy = cyz / a.nz, cz = cyz - cy * a.nz;
+    if (tid < 3 * N) {
+      const int ax = tid / N, i = tid - ax * N;
+      const int d = d1[ax * N + i];
+      const int c = ax == 0 ? cx : (ax == 1 ? cy : cz), m = ax == 0 ? a.nx : (ax == 1 ? a.ny : a.nz);
+      src_ax[ax][i] = wrap_sub(c, d, m);
+    }
+    __syncthreads();
+    const T* fown = fin + size_t(cell) * NV;
+    T* fo = fout + size_t(cell) * NV;
+    constexpr int MM = CS::M, H = CS::H, YH = CS::YH;
+    // an opaque copy of the thread index per cell: the per-velocity offsets and abscissae
+    // below are formed where they are used instead of being hoisted out of the cell loop
+    int tcell = tid;
+    asm volatile("" : "+v"(tcell));
+    const int ix0 = tcell / (N * N), iy0 = (tcell / N) % YH, iz = tcell % N;
+    // velocity k of this cell comes from the source cell (sx[ix], sy[iy], sz[iz]), element
+    // (sx nyz + row(iy, iz)) NV + k.  With m = 1 the x index of value u is the same over
+    // the workgroup, so the source plane sx nyz NV is a scalar base and the rest a 32-bit
+    // offset (a y-z plane of the box holds fewer than 2^31 values)
+    int row[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) row[h] = src_ax[1][iy0 + h * YH] * a.nz + src_ax[2][iz];
+    auto load_shifted = [&](int u) -> T {
+      if constexpr (MM == 1) {
+        const int sx = __builtin_amdgcn_readfirstlane(src_ax[0][u / H]);
+        const T* plane = fin + size_t(sx) * size_t(nyz) * NV;
+        return plane[uint32_t(row[u % H]) * NV + uint32_t(u * NTH + tcell)];
+      } else {
+        return fin[(size_t(src_ax[0][(u / H) * MM + ix0]) * nyz + size_t(row[u % H])) * NV + size_t(u * NTH + tcell)];
+      }
+    };
+    // The values stream in batches of B (the loads of a batch are all issued before any is
+    // used); the relaxation streams the shifted masses a second time after the per-cell
+    // setup (from L2 or the last-level cache) instead of holding them in registers across it.
+    constexpr int B = CS::B;
+    const double vz = -a.L + double(iz) * dv;
+    // eq. DM_update: the sister particle of every moved velocity.  The own-cell value is
+    // read for every velocity: for one that did not move it is the value just loaded as f*
+    // (same address: a cache hit) and its difference is exactly zero, which leaves the
+    // FP64 sums unchanged, so no branch holds the loads back.  Per y half the thread's y
+    // and z abscissae are fixed, so the five moments of the differences follow from three
+    // sums with the exact integer weights ix, ix^2 (v_x = -L + ix dv):
+    // sum d v_x = -L D0 + dv D1, sum d v_x^2 = L^2 D0 - 2 L dv D1 + dv^2 D2
+    double d0[H], d1s[H], d2[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) d0[h] = d1s[h] = d2[h] = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < nv; k0 += NTH * UNR) {
-      T vs[UNR];
+    for (int u0 = 0; u0 < VPT; u0 += B) {
+      T xs[B], vo[B];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * NTH + tid;
-        vs[u] = T(0);
-        if (k < nv)
-          vs[u] = fin[source_index(cx, cy, cz, dl[3 * k + 0], dl[3 * k + 1], dl[3 * k + 2], a.nx, a.ny, a.nz, nv, k)];
+      for (int j = 0; j < B; ++j) {
+        xs[j] = load_shifted(u0 + j);
+        if constexpr (DM) vo[j] = fown[uint32_t((u0 + j) * NTH + tcell)];
       }
+      if constexpr (!BGK) {
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * NTH + tid;
-        if (k >= nv) continue;
-        const int ix = k / (N * N), iy = (k / N) % N, iz = k % N;
-        const R vx = -Lr + R(ix) * dvr, vy = -Lr + R(iy) * dvr, vz = -Lr + R(iz) * dvr;
-        const R corr = R(1) + sp[3] + sp[4] * vx + sp[5] * vy + sp[6] * vz +
-                       sp[7] * (R(0.5) * (vx * vx + vy * vy + vz * vz));
-        const R E = pref * sp[8 + ix] * sp[8 + N + iy] * sp[8 + 2 * N + iz] * corr;
-        const R x = vs[u];
-        const T out = MODE == 2 ? E + (x - E) * rate : x + rate * (E - x);
-        fo[k] = out;
-        if constexpr (EXTRAS) {
-          if (q) q[size_t(cell) * nv + k] = nu_c * (E - x);
-        }
-        if (EXTRAS && a.moments) {
-          const double d = double(out);
-          const double wx = -a.L + double(ix) * dv, wy = -a.L + double(iy) * dv, wz = -a.L + double(iz) * dv;
-          mom[0] += d;
-          mom[1] += d * wx;
-          mom[2] += d * wy;
-          mom[3] += d * wz;
-          mom[4] += d * (0.5 * (wx * wx + wy * wy + wz * wz));
+        for (int j = 0; j < B; ++j) fo[uint32_t((u0 + j) * NTH + tcell)] = xs[j];
+      }
+      if constexpr (DM) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int h = j % H;   // B is a multiple of H
+          const double diff = double(xs[j]) - double(vo[j]);
+          const double ixd = double(((u0 + j) / H) * MM + ix0);
+          d0[h] += diff;
+          d1s[h] += diff * ixd;
+          d2[h] += diff * (ixd * ixd);
         }
       }
     }
-    if (EXTRAS && a.moments) {
-      block_sum5(mom, red);
-      if (tid == 0)
-        for (int i = 0; i < 5; ++i) a.moments[cell * 5 + i] = mom[i] * w3;
+    if constexpr (DM) {
+      double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const double vy = -a.L + double(iy0 + h * YH) * dv;
+        const double sx1 = -a.L * d0[h] + dv * d1s[h];
+        const double sx2 = a.L * a.L * d0[h] - 2.0 * a.L * dv * d1s[h] + dv * dv * d2[h];
+        acc[0] += d0[h];
+        acc[1] += sx1;
+        acc[2] += vy * d0[h];
+        acc[3] += vz * d0[h];
+        acc[4] += 0.5 * (sx2 + (vy * vy + vz * vz) * d0[h]);
+      }
+      block_sum5(acc, red);
+      if (tid == 0) {
+        double U[5], W[5];
+        for (int i = 0; i < 5; ++i) {
+          U[i] = a.cons[size_t(cell) * 5 + i] + acc[i] * w3;
+          a.cons[size_t(cell) * 5 + i] = U[i];
+        }
+        to_primitive(U, W);
+        if (a.prim)
+          for (int i = 0; i < 5; ++i) a.prim[size_t(cell) * 5 + i] = W[i];
+        for (int i = 0; i < 5; ++i) {
+          Ush[i] = U[i];
+          Wsh[i] = W[i];
+        }
+      }
     }
-    __syncthreads();  // LDS of this cell is reused by the next one
+    if constexpr (BGK) {
+      // the cell's Maxwellian: Gaussian factors and their powers, the 1-D moments, the
+      // Gram matrix and lambda, each step spread over threads through LDS
+      __syncthreads();
+      if (tid < 3 * N) {
+        const int ax = tid / N, i = tid - ax * N;
+        const double v = -a.L + double(i) * dv;
+        const double d = v - Wsh[1 + ax];
+        const double g = exp(-d * d / (2.0 * Wsh[4]));
+        gr[tid] = R(g);
+        double gp = g;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+          gpow[ax][p][i] = gp;   // g v^p
+          gp *= v;
+        }
+      }
+      __syncthreads();
+      if (tid < 15) {
+        const int ax = tid / 5, p = tid - ax * 5;
+        double m = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < N; ++i) m += gpow[ax][p][i];
+        Ash[ax][p] = m;
+      }
+      __syncthreads();
+      if (tid < 25) {
+        const int i = tid / 5, j = tid - i * 5;
+        if (i <= j) Gsh[i][j] = gram_entry(i, j, Ash);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double tt = 2.0 * 3.14159265358979323846 * Wsh[4];
+        const double pref_d = Wsh[0] / (tt * sqrt(tt));
+        double lam[5];
+        for (int i = 0; i < 5; ++i) lam[i] = Ush[i] / (pref_d * w3) - Gsh[0][i];
+        solve5(Gsh, lam);
+        const double nu = a.nu_density ? a.nu * Wsh[0] : a.nu;
+        par[0] = pref_d;
+        par[1] = nu;
+        par[2] = MODE == 2 ? exp(-nu * a.dt) : nu * a.dt;
+        for (int i = 0; i < 5; ++i) par[3 + i] = lam[i];
+      }
+      __syncthreads();
+      const R pref = R(par[0]), nu_c = R(par[1]), rate = R(par[2]);
+      const R l1 = R(par[4]), l4 = R(par[7]);
+      const R Lr = R(a.L), dvr = R(dv);
+      const R rz = -Lr + R(iz) * dvr;
+      // per y half: the factors that do not depend on v_x
+      R pyz[H], cyz[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int iy = iy0 + h * YH;
+        const R ry = -Lr + R(iy) * dvr;
+        pyz[h] = pref * gr[N + iy] * gr[2 * N + iz];
+        cyz[h] = R(1) + R(par[3]) + R(par[5]) * ry + R(par[6]) * rz + l4 * (R(0.5) * (ry * ry + rz * rz));
+      }
+      double mom[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+      for (int u0 = 0; u0 < VPT; u0 += B) {
+        T xs[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) xs[j] = load_shifted(u0 + j);
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int h = j % H, ix = ((u0 + j) / H) * MM + ix0, k = (u0 + j) * NTH + tcell;
+          const R rx = -Lr + R(ix) * dvr;
+          const R corr = cyz[h] + l1 * rx + l4 * (R(0.5) * (rx * rx));
+          const R E = pyz[h] * gr[ix] * corr;
+          const R x = xs[j];
+          const T out = MODE == 2 ? E + (x - E) * rate : x + rate * (E - x);
+          fo[uint32_t(k)] = out;
+          if constexpr (EXTRAS) {
+            if (q) q[size_t(cell) * NV + k] = nu_c * (E - x);
+            if (a.moments) {
+              const double d = double(out);
+              const double vx = -a.L + double(ix) * dv, vy = -a.L + double(iy0 + h * YH) * dv;
+              mom[0] += d;
+              mom[1] += d * vx;
+              mom[2] += d * vy;
+              mom[3] += d * vz;
+              mom[4] += d * (0.5 * (vx * vx + vy * vy + vz * vz));
+            }
+          }
+        }
+      }
+      if (EXTRAS && a.moments) {
+        block_sum5(mom, red);
+        if (tid == 0)
+          for (int i = 0; i < 5; ++i) a.moments[size_t(cell) * 5 + i] = mom[i] * w3;
+      }
+    }
+    __syncthreads();  // the per-cell tables are rewritten for the next cell
   }
 }
 
@@ -377,10 +448,10 @@ __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, T* __re
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-hipError_t launch_xport_reset(const XportState& st, int nv, void* stream) {
-  const int m = 3 * nv;
+hipError_t launch_xport_reset(const XportState& st, int n, void* stream) {
+  const int m = 3 * n * n * n;
   hipLaunchKernelGGL(k_xport_reset, dim3((m + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), st.s,
-                     st.o, st.dl, m);
+                     st.o, st.dl, st.d1, m, 3 * n);
   return hipGetLastError();
 }
 
@@ -388,54 +459,40 @@ hipError_t launch_xport_advance(const XportState& st, int n, double L, double dt
   const int nv = n * n * n;
   prof_mark(kProfAdvance, true, static_cast<hipStream_t>(stream));
   hipLaunchKernelGGL(k_xport_advance, dim3((nv + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     st.s, st.o, st.dl, n, L, dt, dx);
+                     st.s, st.o, st.dl, st.d1, n, L, dt, dx);
   prof_mark(kProfAdvance, false, static_cast<hipStream_t>(stream));
   return hipGetLastError();
 }
 
-hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int nv, int nx, int ny,
-                       int nz, void* stream) {
-  const int bpc = (nv + 255) / 256;
-  const long cells = long(nx) * ny * nz;
-  // at most 2^22 blocks (2^30 threads); each block strides over its cells
-  const long max_cells = (1L << 22) / bpc > 0 ? (1L << 22) / bpc : 1;
-  const dim3 grid(unsigned((cells < max_cells ? cells : max_cells) * bpc));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  prof_mark(kProfRoll, true, st);
-  if (dtype_is_f32)
-    hipLaunchKernelGGL(k_roll<float>, grid, dim3(256), 0, st, static_cast<const float*>(fin),
-                       static_cast<float*>(fout), dl, nv, nx, ny, nz, bpc);
-  else
-    hipLaunchKernelGGL(k_roll<double>, grid, dim3(256), 0, st, static_cast<const double*>(fin),
-                       static_cast<double*>(fout), dl, nv, nx, ny, nz, bpc);
-  prof_mark(kProfRoll, false, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* dl, int dm, int mode,
-                            const StepCellArgs& a, void* stream) {
+// mode: 0 DM update + shift, 1 DM + Euler BGK, 2 DM + exact BGK, 3 shift only
+static hipError_t launch_cell_step(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
+                                   const StepCellArgs& a, hipStream_t st) {
   const int64_t cells = int64_t(a.nx) * a.ny * a.nz;
-  const dim3 grid(unsigned(cells < (int64_t(1) << 20) ? cells : (int64_t(1) << 20)));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  // the relaxation needs the DM-updated U; without a relaxation this is the DM update only
-  if (!dm) return hipErrorInvalidValue;
+  if (mode != 3 && !a.cons) return hipErrorInvalidValue;
   auto go = [&](auto tag, auto nc) -> hipError_t {
     using T = decltype(tag);
     constexpr int NN = decltype(nc)::value;
+    constexpr int NTH = CellShape<T, NN>::NTH;
+    // one workgroup per cell, in rounds of at most 2^32 / NTH work-items; a multiple of 8
+    // workgroups so that each XCD gets the same share of every round
+    const int64_t cap = ((int64_t(1) << 31) / NTH) & ~int64_t(7);
+    const int64_t want = (cells + 7) & ~int64_t(7);
+    const dim3 grid(unsigned(want < cap ? want : cap)), block(NTH);
     const T* fi = static_cast<const T*>(fin);
     T* fo = static_cast<T*>(fout);
-    hipLaunchKernelGGL((k_dm_update<T, NN>), grid, dim3(kStreamThreads), 0, st, fi, dl, a);
-    if (mode == 0) return hipGetLastError();
-    const dim3 sgrid(unsigned((cells + 255) / 256));
     const bool extras = a.q || a.moments;
-    if (mode == 1) {
-      hipLaunchKernelGGL((k_bgk_setup<T, NN, 1>), sgrid, dim3(256), 0, st, fo, a);
-      if (extras) hipLaunchKernelGGL((k_bgk_relax<T, NN, 1, true>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
-      else hipLaunchKernelGGL((k_bgk_relax<T, NN, 1, false>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
-    } else {
-      hipLaunchKernelGGL((k_bgk_setup<T, NN, 2>), sgrid, dim3(256), 0, st, fo, a);
-      if (extras) hipLaunchKernelGGL((k_bgk_relax<T, NN, 2, true>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
-      else hipLaunchKernelGGL((k_bgk_relax<T, NN, 2, false>), grid, dim3(kStreamThreads), 0, st, fi, fo, dl, a);
+    switch (mode) {
+      case 0: hipLaunchKernelGGL((k_cell_step<T, NN, 0, false>), grid, block, 0, st, fi, fo, d1, a); break;
+      case 1:
+        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 1, true>), grid, block, 0, st, fi, fo, d1, a);
+        else hipLaunchKernelGGL((k_cell_step<T, NN, 1, false>), grid, block, 0, st, fi, fo, d1, a);
+        break;
+      case 2:
+        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 2, true>), grid, block, 0, st, fi, fo, d1, a);
+        else hipLaunchKernelGGL((k_cell_step<T, NN, 2, false>), grid, block, 0, st, fi, fo, d1, a);
+        break;
+      case 3: hipLaunchKernelGGL((k_cell_step<T, NN, 3, false>), grid, block, 0, st, fi, fo, d1, a); break;
+      default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   };
@@ -449,8 +506,30 @@ hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const
       default: return hipErrorInvalidValue;
     }
   };
+  return dtype_is_f32 ? by_n(float{}) : by_n(double{});
+}
+
+hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int n, double L, int nx,
+                       int ny, int nz, void* stream) {
+  StepCellArgs a{};
+  a.n = n;
+  a.L = L;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   prof_mark(kProfRoll, true, st);
-  const hipError_t e = dtype_is_f32 ? by_n(float{}) : by_n(double{});
+  const hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, 3, a, st);
+  prof_mark(kProfRoll, false, st);
+  return e;
+}
+
+hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
+                            const StepCellArgs& a, void* stream) {
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  prof_mark(kProfRoll, true, st);
+  const hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, mode, a, st);
   prof_mark(kProfRoll, false, st);
   return e;
 }
