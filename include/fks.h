@@ -142,7 +142,12 @@ fks_status fks_heun(fks_plan plan, void* f, void* f_tmp1, void* f_tmp2, double d
 fks_status fks_moments(fks_plan plan, const void* f, int64_t n_cells, double* d_u, void* stream);
 
 /* Uneven batch: n_groups plans (each its own n, same dtype), group g evaluates
- * q[g] = Q(f[g]) on n_cells[g] cells.  All groups are enqueued on `stream` back to back. */
+ * q[g] = Q(f[g]) on n_cells[g] cells.  The groups run concurrently: the first non-empty
+ * group on `stream`, each further one (at most 7) on a library-owned side stream forked
+ * from `stream` by an event and joined back before the call returns, so work enqueued on
+ * `stream` afterwards sees every q[g]; under stream capture the fork and join are graph
+ * edges.  Groups whose plans share a workspace run one after another on `stream`.  The
+ * side streams (default priority) and events are created once per device and kept. */
 fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const void* const* f,
                                void* const* q, const int64_t* n_cells, void* stream);
 
@@ -243,8 +248,6 @@ fks_status fks_step_ex(fks_plan plan, fks_xport xp, void* f, void* f_tmp, double
 
 void fks_xport_destroy(fks_xport xp);
 
-/* ---- stream capture ---------------------------------------------------------------- */
-
 /* ---- Learned surrogate of Q (an extension beyond the paper) ----------------------
  *
  * A multilayer perceptron maps the low Fourier modes of a cell's distribution to its
@@ -317,6 +320,8 @@ fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t 
 fks_status fks_sur_infer(fks_sur s, fks_plan plan, const void* f, float* q, int64_t n_cells, double threshold,
                          int64_t* n_fallback, double* d_indicator, void* stream);
 void fks_sur_destroy(fks_sur s);
+
+/* ---- stream capture ---------------------------------------------------------------- */
 
 /* Records every library call enqueued on `stream` between fks_graph_begin and
  * fks_graph_end into one hipGraph (no device work runs while recording), so that a

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string>
@@ -579,6 +580,39 @@ fks_status fks_plan_info(fks_plan p, int32_t* n_terms, int32_t* pad) {
   return ok();
 }
 
+// Side streams for concurrent groups, per device, created once and kept until the process
+// ends (default priority, non-blocking), with one fork event and one join event per side
+// stream (timing disabled).
+namespace {
+constexpr int kMaxSide = 7;
+struct SidePool {
+  std::mutex use;  // one fork/join at a time per device (the events are shared)
+  bool ready = false;
+  hipStream_t s[kMaxSide] = {};
+  hipEvent_t fork = nullptr, join[kMaxSide] = {};
+};
+std::mutex g_side_mu;
+SidePool g_side[64];
+
+// Creates the current device's side streams (idempotent); false if they cannot be made.
+bool side_pool_init(SidePool** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SidePool& sp = g_side[dev];
+  if (!sp.ready) {
+    if (hipEventCreateWithFlags(&sp.fork, hipEventDisableTiming) != hipSuccess) return false;
+    for (int i = 0; i < kMaxSide; ++i) {
+      if (hipStreamCreateWithFlags(&sp.s[i], hipStreamNonBlocking) != hipSuccess) return false;
+      if (hipEventCreateWithFlags(&sp.join[i], hipEventDisableTiming) != hipSuccess) return false;
+    }
+    sp.ready = true;
+  }
+  *out = &sp;
+  return true;
+}
+}  // namespace
+
 fks_status fks_plan_bind(fks_plan p, void* d_tables, size_t table_bytes, void* d_workspace, size_t workspace_bytes,
                          void* stream) {
   if (!p || !d_tables) return fail(FKS_E_ARG, "null argument");
@@ -600,6 +634,10 @@ fks_status fks_plan_bind(fks_plan p, void* d_tables, size_t table_bytes, void* d
   p->d_tables = d_tables;
   p->d_ws = d_workspace;
   p->bound = true;
+  // the side streams of concurrent grouped calls, made here (outside any stream capture);
+  // without them grouped calls run their groups one after another
+  SidePool* sp = nullptr;
+  (void)side_pool_init(&sp);
   return ok();
 }
 
@@ -677,11 +715,52 @@ fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const vo
       return fail(FKS_E_ARG, "group %d: bad buffers or count", g);
     if (plans[g]->d.dtype != plans[0]->d.dtype) return fail(FKS_E_ARG, "groups must share one dtype");
   }
-  for (int g = 0; g < n_groups; ++g) {
-    fks_status s = fks_collide(plans[g], f[g], q[g], n_cells[g], stream);
+  // Groups run concurrently, group 0 on the caller's stream and group g > 0 on a side
+  // stream forked from it by an event and joined back before the call returns, so the
+  // smaller groups fill the CUs the largest leaves idle (its launch tails, its forward and
+  // synthesis kernels).  Under stream capture the fork and join become graph edges.  Groups
+  // that share a workspace (the same plan twice, or overlapping buffers) run one after
+  // another on the caller's stream.
+  std::vector<int> active;
+  for (int g = 0; g < n_groups; ++g)
+    if (n_cells[g] > 0) active.push_back(g);
+  bool concurrent = active.size() > 1 && int(active.size()) - 1 <= kMaxSide;
+  for (size_t i = 0; concurrent && i < active.size(); ++i)
+    for (size_t j = i + 1; j < active.size(); ++j) {
+      const fks_plan a = plans[active[i]], b = plans[active[j]];
+      const uintptr_t xa = reinterpret_cast<uintptr_t>(a->d_ws), xb = reinterpret_cast<uintptr_t>(b->d_ws);
+      if (a == b || (xa < xb + b->ws_bytes && xb < xa + a->ws_bytes)) concurrent = false;
+    }
+  SidePool* sp = nullptr;
+  if (concurrent && !side_pool_init(&sp)) concurrent = false;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!concurrent) {
+    for (int g : active) {
+      fks_status s = fks_collide(plans[g], f[g], q[g], n_cells[g], stream);
+      if (s != FKS_OK) return s;
+    }
+    return ok();
+  }
+  std::lock_guard<std::mutex> lk(sp->use);
+  fks_status s = check_hip(hipEventRecord(sp->fork, st), "fork event");
+  if (s != FKS_OK) return s;
+  for (size_t i = 1; i < active.size(); ++i) {
+    s = check_hip(hipStreamWaitEvent(sp->s[i - 1], sp->fork, 0), "fork wait");
     if (s != FKS_OK) return s;
   }
-  return ok();
+  fks_status first_err = FKS_OK;
+  for (size_t i = 0; i < active.size(); ++i) {
+    const int g = active[i];
+    s = fks_collide(plans[g], f[g], q[g], n_cells[g], i == 0 ? stream : static_cast<void*>(sp->s[i - 1]));
+    if (s != FKS_OK && first_err == FKS_OK) first_err = s;
+  }
+  // join every side stream back, also after an error, so no capture is left forked
+  for (size_t i = 1; i < active.size(); ++i) {
+    s = check_hip(hipEventRecord(sp->join[i - 1], sp->s[i - 1]), "join event");
+    if (s == FKS_OK) s = check_hip(hipStreamWaitEvent(st, sp->join[i - 1], 0), "join wait");
+    if (s != FKS_OK && first_err == FKS_OK) first_err = s;
+  }
+  return first_err == FKS_OK ? ok() : first_err;
 }
 
 fks_status fks_heun(fks_plan p, void* f, void* f_tmp1, void* f_tmp2, double dt, int32_t n_steps, int64_t n_cells,

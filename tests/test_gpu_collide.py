@@ -169,6 +169,25 @@ def test_grouped_uneven_batch():
         assert_parity(q.double().cpu().numpy(), r, TOL["f32"], "grouped")
 
 
+def test_grouped_concurrent_equals_one_by_one():
+    # the groups run on forked streams; each group's result is bit for bit that of its own
+    # call.  A plan given twice shares its workspace, so that call runs the groups in turn.
+    from paper_1701_01608_amd import collide_grouped
+    fs, plans = [], []
+    for n, seed in ((32, 21), (16, 22), (24, 23), (16, 24)):
+        plans.append(gpu_plan(n, "f32", a1=3, a2=4, max_cells=40))
+        fs.append(torch.tensor(fks_inputs.maxwellian_mixture(n, 8.0, 40, seed=seed), dtype=torch.float32,
+                               device="cuda"))
+    one = [p.collide(f) for p, f in zip(plans, fs)]
+    together = collide_grouped(plans, fs)
+    shared = collide_grouped([plans[1], plans[1]], [fs[1], fs[3][:7].contiguous()])
+    torch.cuda.synchronize()
+    for a, b in zip(one, together):
+        assert torch.equal(a, b)
+    assert torch.equal(shared[0], one[1])
+    assert torch.equal(shared[1], plans[1].collide(fs[3][:7].contiguous()))
+
+
 def test_full_batch_4096_sampled():
     # the benchmark workload (4096 cells, n=32, M=16, FP32) in the same launch
     # configuration; sampled cells against the oracle, mass of every cell
