@@ -141,6 +141,14 @@ fks_status fks_heun(fks_plan plan, void* f, void* f_tmp1, void* f_tmp2, double d
 /* FP64 moments of f: d_u[c][0..4] = dv^3 sum_k phi(v_k) f[c][k], phi = (1, v, |v|^2/2). */
 fks_status fks_moments(fks_plan plan, const void* f, int64_t n_cells, double* d_u, void* stream);
 
+/* Normalised non-equilibrium residual of f per cell (the moments of Section 3 one order
+ * further): with rho, u, T the density, mean velocity and temperature of f, c = v - u,
+ * sigma_ij = dv^3 sum_k f c_i c_j - rho T delta_ij (deviatoric stress) and
+ * q_i = dv^3 sum_k f |c|^2 c_i / 2 (heat flux), d_r[c] = |sigma|_F / (rho T) + |q| / (rho T^1.5)
+ * (device FP64, [n_cells]); zero for a Maxwellian, invariant under f -> a f and under
+ * velocity shifts.  Only the plan's grid (n, L, dtype) is used; no binding needed. */
+fks_status fks_noneq(fks_plan plan, const void* f, int64_t n_cells, double* d_r, void* stream);
+
 /* Uneven batch: n_groups plans (each its own n, same dtype), group g evaluates
  * q[g] = Q(f[g]) on n_cells[g] cells.  The groups run concurrently: the first non-empty
  * group on `stream`, each further one (at most 7) on a library-owned side stream forked
@@ -319,6 +327,16 @@ fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t 
  * cells (to read the fallback count). */
 fks_status fks_sur_infer(fks_sur s, fks_plan plan, const void* f, float* q, int64_t n_cells, double threshold,
                          int64_t* n_fallback, double* d_indicator, void* stream);
+/* As fks_sur_infer, but the fallback takes a share of the cells ranked by an absolute error
+ * estimate: a_j = r_j ||Q_j||_2 (the relative moment residual times the norm of the
+ * surrogate's Q), and in every chunk of c <= max_batch cells the ceil(fallback_frac c)
+ * cells with the largest a_j (all cells tied with the last one, and every NaN) take the
+ * spectral Q.  A batch error budget is met with fewer fallbacks this way than by a
+ * threshold on r_j, since the batch rel-L2 is dominated by the cells with the largest Q.
+ * d_indicator (optional) receives a_j.  fallback_frac outside [0, 1]: FKS_E_ARG.
+ * Synchronises `stream` twice per chunk (the residuals, the count). */
+fks_status fks_sur_infer_ranked(fks_sur s, fks_plan plan, const void* f, float* q, int64_t n_cells,
+                                double fallback_frac, int64_t* n_fallback, double* d_indicator, void* stream);
 void fks_sur_destroy(fks_sur s);
 
 /* ---- stream capture ---------------------------------------------------------------- */

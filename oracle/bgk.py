@@ -84,3 +84,21 @@ def relax_euler(f, E, nu, dt):
 
 def relax_exact(f, E, nu, dt):
     return E + (f - E) * np.exp(-nu * dt)
+
+
+def noneq_residual(f, g: Grid):
+    """Normalised non-equilibrium residual of one cell's f (FP64), from its central moments:
+    with rho, u, T of f and c = v - u, the deviatoric stress
+    sigma = dv^3 sum f c c^T - rho T I and the heat flux q = dv^3 sum f |c|^2 c / 2 vanish for a
+    Maxwellian; r = |sigma|_F / (rho T) + |q| / (rho T^{3/2})."""
+    f = np.asarray(f, dtype=np.float64).reshape(-1)
+    V = velocity_vectors(g).reshape(-1, 3)
+    w = g.dv ** 3
+    rho = w * f.sum()
+    u = w * (f @ V) / rho
+    c = V - u
+    P = w * (c * f[:, None]).T @ c
+    T = np.trace(P) / (3.0 * rho)
+    sigma = P - rho * T * np.eye(3)
+    q = 0.5 * w * ((np.sum(c * c, axis=1) * f) @ c)
+    return float(np.linalg.norm(sigma) / (rho * T) + np.linalg.norm(q) / (rho * T ** 1.5))

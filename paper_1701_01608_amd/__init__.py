@@ -175,6 +175,17 @@ class Plan:
         _lib.check(_lib.lib().fks_moments(self._h, _ptr(f), cells, _ptr(out), _stream_ptr(stream)))
         return out
 
+    def noneq(self, f, out=None, stream=None):
+        """Normalised non-equilibrium residual per cell (deviatoric stress and heat flux), FP64."""
+        cells = self._check_f(f)
+        if out is None:
+            if _recording() is not None:
+                raise FKSError(-1, "inside a Graph recording, pass out explicitly")
+            out = torch.empty((cells,), dtype=torch.float64, device=f.device)
+        _hold(self, f, out)
+        _lib.check(_lib.lib().fks_noneq(self._h, _ptr(f), cells, _ptr(out), _stream_ptr(stream)))
+        return out
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib._lib is not None:
@@ -297,6 +308,20 @@ class Surrogate:
         nf = ctypes.c_int64()
         _lib.check(_lib.lib().fks_sur_infer(self._h, plan.handle, _ptr(f), _ptr(q), cells, float(threshold),
                                             ctypes.byref(nf), _ptr(indicator), _stream_ptr(stream)))
+        return q, nf.value
+
+    def infer_ranked(self, plan, f, fallback_frac, q=None, indicator=None, stream=None):
+        """Q of FP32 cells f: surrogate, with the spectral fallback for the share fallback_frac
+        of each chunk's cells that have the largest absolute residual (relative moment
+        residual times ||Q||).  Returns (q, number of fallback cells)."""
+        _no_recording("Surrogate.infer_ranked")
+        cells = plan._check_f(f)
+        if q is None:
+            q = torch.empty_like(f)
+        nf = ctypes.c_int64()
+        _lib.check(_lib.lib().fks_sur_infer_ranked(self._h, plan.handle, _ptr(f), _ptr(q), cells,
+                                                   float(fallback_frac), ctypes.byref(nf), _ptr(indicator),
+                                                   _stream_ptr(stream)))
         return q, nf.value
 
     def __del__(self):

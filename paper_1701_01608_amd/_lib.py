@@ -61,6 +61,7 @@ _SIGS = {
     "fks_collide_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fks_relax": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int64, _VP, _VP]),
     "fks_moments": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
+    "fks_noneq": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
     "fks_heun": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, _VP]),
     "fks_graph_begin": (ctypes.c_int, [_VP]),
     "fks_graph_end": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
@@ -96,6 +97,8 @@ _SIGS = {
     "fks_sur_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _VP,
                                           _VP]),
     "fks_sur_infer": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_int64), _VP, _VP]),
+    "fks_sur_infer_ranked": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double,
                                      ctypes.POINTER(ctypes.c_int64), _VP, _VP]),
     "fks_sur_destroy": (None, [_VP]),
     "fks_profile_start": (ctypes.c_int, []),

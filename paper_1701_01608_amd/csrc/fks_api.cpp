@@ -2,7 +2,9 @@
 // construction (Appendix A of the paper), workspace layout and launch sequencing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -705,6 +707,18 @@ fks_status fks_moments(fks_plan p, const void* f, int64_t n_cells, double* d_u, 
              : FKS_E_DEVICE;
 }
 
+fks_status fks_noneq(fks_plan p, const void* f, int64_t n_cells, double* d_r, void* stream) {
+  if (!p) return fail(FKS_E_ARG, "null plan");
+  if (n_cells < 0) return fail(FKS_E_ARG, "n_cells < 0");
+  if (n_cells == 0) return ok();
+  if (!f || !d_r) return fail(FKS_E_ARG, "null f or d_r");
+  if (n_cells > (int64_t(1) << 31) - 1) return fail(FKS_E_ARG, "too many cells for one call");
+  return check_hip(fks::launch_noneq(p->d.dtype == FKS_F32, p->n, f, n_cells, p->d.L, d_r, stream),
+                   "non-equilibrium residual") == FKS_OK
+             ? ok()
+             : FKS_E_DEVICE;
+}
+
 fks_status fks_collide_grouped(const fks_plan* plans, int32_t n_groups, const void* const* f, void* const* q,
                                const int64_t* n_cells, void* stream) {
   if (!plans || !f || !q || !n_cells || n_groups < 0) return fail(FKS_E_ARG, "null argument");
@@ -1225,7 +1239,7 @@ fks_status fks_sur_targets(fks_sur s, fks_plan p, const float* q, const float* r
   if (n_cells == 0) return ok();
   if (n_cells > (int64_t(1) << 31) - 1) return fail(FKS_E_ARG, "too many cells");
   if (s->center)
-    st = check_hip(fks::launch_shift(s->n, q, s->fout, t, mom, +1, p->d.L, rho, s->scale, 2, nullptr, n_cells, stream),
+    st = check_hip(fks::launch_shift(s->n, q, s->fout, t, mom, +1, p->d.L, rho, s->scale, 2, nullptr, 0, n_cells, stream),
                    "centred targets");
   else
     st = check_hip(fks::launch_sur_target(q, rho, 1.0f / s->scale, t, s->fout, n_cells, stream), "targets");
@@ -1273,8 +1287,12 @@ fks_status fks_sur_train_step(fks_sur s, const void* x, const float* t, int64_t 
   return st == FKS_OK ? ok() : st;
 }
 
-fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t n_cells, double threshold,
-                         int64_t* n_fallback, double* d_indicator, void* stream) {
+// Surrogate inference with the spectral fallback, per chunk of max_batch cells.  ranked = 0:
+// the cells whose relative moment residual exceeds `level` (a threshold) fall back;
+// ranked = 1: the ceil(level * c) cells of each chunk of c cells with the largest absolute
+// residual (relative residual times ||q_sur||_2) fall back.
+static fks_status sur_infer_impl(fks_sur s, fks_plan p, const void* f, float* q, int64_t n_cells, int ranked,
+                                 double level, int64_t* n_fallback, double* d_indicator, void* stream) {
   fks_status st = sur_ready(s);
   if (st != FKS_OK) return st;
   st = check_plan_ready(p);
@@ -1282,10 +1300,12 @@ fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t
   if (p->n != s->n || p->d.dtype != FKS_F32) return fail(FKS_E_ARG, "fallback plan must be FP32 on the same grid");
   if (n_cells < 0 || (n_cells > 0 && (!f || !q))) return fail(FKS_E_ARG, "bad buffers");
   if (n_cells > 0 && ranges_overlap(f, q, size_t(n_cells) * s->fout * 4)) return fail(FKS_E_ARG, "q must not overlap f");
+  if (ranked && !(level >= 0.0 && level <= 1.0)) return fail(FKS_E_ARG, "fallback fraction must be in [0, 1]");
   if (n_fallback) *n_fallback = 0;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const int n3 = s->fout;
   const size_t cell_bytes = size_t(n3) * 4;
+  std::vector<double> h_r;
   for (int64_t c0 = 0; c0 < n_cells; c0 += s->max_batch) {
     const int64_t c = (n_cells - c0 < s->max_batch) ? (n_cells - c0) : s->max_batch;
     const int64_t rows = (c + 127) / 128 * 128;
@@ -1299,17 +1319,34 @@ fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t
     if (st == FKS_OK) {
       const float* y = reinterpret_cast<const float*>(B(s->d_ws, s->w_y));
       if (s->center)  // back from the mean-velocity frame: q(v) = scale rho^2 y(v - u)
-        st = check_hip(fks::launch_shift(s->n, y, n3, qc, mom, -1, p->d.L, rho, s->scale, 1, r, c, stream),
+        st = check_hip(fks::launch_shift(s->n, y, n3, qc, mom, -1, p->d.L, rho, s->scale, 1, r, ranked, c, stream),
                        "surrogate output");
       else
-        st = check_hip(fks::launch_sur_output(y, n3, rho, s->scale, s->n, p->d.L, qc, r, c, stream),
+        st = check_hip(fks::launch_sur_output(y, n3, rho, s->scale, s->n, p->d.L, qc, r, ranked, c, stream),
                        "surrogate output");
     }
     if (st != FKS_OK) return st;
-    if (!(threshold >= 0.0)) continue;  // negative threshold: no fallback
+    double thr = level;
+    if (ranked) {
+      // the k-th largest absolute residual of the chunk on the host (the chunk is
+      // synchronised once anyway, for the fallback count); the k cells above the next
+      // smaller value fall back (ties at the boundary all fall back; NaN always does)
+      const int64_t k = int64_t(std::ceil(level * double(c)));
+      if (k <= 0) continue;
+      h_r.resize(size_t(c));
+      st = check_hip(hipMemcpyAsync(h_r.data(), r, size_t(c) * 8, hipMemcpyDeviceToHost, hs), "indicator copy");
+      if (st == FKS_OK) st = check_hip(hipStreamSynchronize(hs), "indicator sync");
+      if (st != FKS_OK) return st;
+      for (double& v : h_r)
+        if (std::isnan(v)) v = HUGE_VAL;
+      std::nth_element(h_r.begin(), h_r.begin() + (k - 1), h_r.end(), std::greater<double>());
+      thr = std::nextafter(h_r[size_t(k - 1)], -HUGE_VAL);
+    } else if (!(level >= 0.0)) {
+      continue;  // negative threshold: no fallback
+    }
     int* list = reinterpret_cast<int*>(B(s->d_ws, s->w_list));
     int* cnt = reinterpret_cast<int*>(B(s->d_ws, s->w_cnt));
-    st = check_hip(fks::launch_compact(r, int(c), threshold, list, cnt, stream), "compact");
+    st = check_hip(fks::launch_compact(r, int(c), thr, list, cnt, stream), "compact");
     int h_cnt = 0;
     if (st == FKS_OK) st = check_hip(hipMemcpyAsync(&h_cnt, cnt, 4, hipMemcpyDeviceToHost, hs), "count");
     if (st == FKS_OK) st = check_hip(hipStreamSynchronize(hs), "count sync");
@@ -1325,6 +1362,16 @@ fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t
     if (n_fallback) *n_fallback += h_cnt;
   }
   return ok();
+}
+
+fks_status fks_sur_infer(fks_sur s, fks_plan p, const void* f, float* q, int64_t n_cells, double threshold,
+                         int64_t* n_fallback, double* d_indicator, void* stream) {
+  return sur_infer_impl(s, p, f, q, n_cells, 0, threshold, n_fallback, d_indicator, stream);
+}
+
+fks_status fks_sur_infer_ranked(fks_sur s, fks_plan p, const void* f, float* q, int64_t n_cells,
+                                double fallback_frac, int64_t* n_fallback, double* d_indicator, void* stream) {
+  return sur_infer_impl(s, p, f, q, n_cells, 1, fallback_frac, n_fallback, d_indicator, stream);
 }
 
 void fks_sur_destroy(fks_sur s) { delete s; }

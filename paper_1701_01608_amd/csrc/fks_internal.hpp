@@ -79,11 +79,13 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, void* p16, 
 hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int half, int npair, int K, int Kh, int mh,
                            double box3, void* X, int ldx, float* rho, const double* mom, double L, int64_t cells,
                            void* stream);
+// r: the moment-residual indicator per cell (relative; with absolute = 1 times the cell's
+// ||q||_2, an absolute error estimate), or null
 hipError_t launch_sur_output(const float* Y, int ldy, const float* rho, float scale, int n, double L, float* q, double* r,
-                             int64_t cells, void* stream);
+                             int absolute, int64_t cells, void* stream);
 hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, float* t, int n3, int64_t cells, void* stream);
 hipError_t launch_shift(int n, const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
-                        const float* rho, float scale, int mode, double* r, int64_t cells, void* stream);
+                        const float* rho, float scale, int mode, double* r, int absolute, int64_t cells, void* stream);
 hipError_t launch_features(int dtype_is_f32, int n, int modes, const void* f, void* X, int ldx, float* rho,
                            double* mom, int center, double L, int64_t cells, void* stream);
 hipError_t launch_compact(const double* r, int cells, double thr, int* list, int* count, void* stream);
@@ -130,6 +132,8 @@ struct StepCellArgs {
 hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
                             const StepCellArgs& a, void* stream);
 hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream);
+// normalised non-equilibrium residual (deviatoric stress, heat flux) per cell
+hipError_t launch_noneq(int dtype_is_f32, int n, const void* f, int64_t cells, double L, double* r, void* stream);
 hipError_t launch_copy(int dtype_is_f32, const void* src, void* dst, int64_t n, void* stream);
 
 }  // namespace fks

@@ -607,16 +607,18 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ f, __bf1
 // r = max_i |sum_k phi_i(v_k) q_k| / (sum_k |phi_i(v_k)| |q_k|), phi = (1, v, |v|^2/2), FP64.
 __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y, int ldy, const float* __restrict__ rho,
                                                     float scale, int n, double L, float* __restrict__ q,
-                                                    double* __restrict__ r_out) {
+                                                    double* __restrict__ r_out, int absolute) {
   __shared__ double red[10][4];
+  __shared__ double rq2[4];
   const int cell = blockIdx.x;
   const size_t N3 = size_t(n) * n * n;
   const double dv = 2.0 * L / n;
   const float r2 = scale * rho[cell] * rho[cell];
-  double s[5] = {0, 0, 0, 0, 0}, a[5] = {0, 0, 0, 0, 0};
+  double s[5] = {0, 0, 0, 0, 0}, a[5] = {0, 0, 0, 0, 0}, q2 = 0.0;
   for (size_t i = threadIdx.x; i < N3; i += blockDim.x) {
     const float qv = Y[size_t(cell) * ldy + i] * r2;
     q[size_t(cell) * N3 + i] = qv;
+    q2 += double(qv) * double(qv);
     const int x = int(i / (size_t(n) * n)), y = int((i / n) % n), z = int(i % n);
     const double vx = -L + x * dv, vy = -L + y * dv, vz = -L + z * dv;
     const double ph[5] = {1.0, vx, vy, vz, 0.5 * (vx * vx + vy * vy + vz * vz)};
@@ -631,11 +633,14 @@ __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y,
       a[k] += __shfl_xor(a[k], off, 64);
     }
   }
-  if ((threadIdx.x & 63) == 0)
+  for (int off = 32; off > 0; off >>= 1) q2 += __shfl_xor(q2, off, 64);
+  if ((threadIdx.x & 63) == 0) {
     for (int k = 0; k < 5; ++k) {
       red[k][threadIdx.x >> 6] = s[k];
       red[5 + k][threadIdx.x >> 6] = a[k];
     }
+    rq2[threadIdx.x >> 6] = q2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = 0.0;
@@ -644,6 +649,7 @@ __global__ __launch_bounds__(256) void k_sur_output(const float* __restrict__ Y,
       const double ak = red[5 + k][0] + red[5 + k][1] + red[5 + k][2] + red[5 + k][3];
       r = fmax(r, fabs(sk) / (ak + 1e-300));
     }
+    if (absolute) r *= sqrt(rq2[0] + rq2[1] + rq2[2] + rq2[3]);
     r_out[cell] = r;
   }
 }
@@ -666,15 +672,15 @@ struct ShiftLds {
   static_assert(bytes <= 156 * 1024, "cell does not fit in LDS");
 };
 
-__device__ __forceinline__ void block_sum10(double (&v)[10], double* red) {
+__device__ __forceinline__ void block_sum11(double (&v)[11], double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = 0; i < 10; ++i) {
+  for (int i = 0; i < 11; ++i) {
     double x = v[i];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0) red[i * 16 + wid] = x;
   }
   __syncthreads();
-  for (int i = 0; i < 10; ++i) {
+  for (int i = 0; i < 11; ++i) {
     double t = 0.0;
     for (int w = 0; w < nw; ++w) t += red[i * 16 + w];
     v[i] = t;
@@ -713,11 +719,11 @@ template <int N>
 __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int64_t ld_in, float* __restrict__ out,
                                                const double* __restrict__ mom, int sign, double L,
                                                const float* __restrict__ rho, float scale, int mode,
-                                               double* __restrict__ r_out) {
+                                               double* __restrict__ r_out, int absolute) {
   using SL = ShiftLds<N>;
   constexpr int RS = SL::RS, KH1 = SL::KH1;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ double red[10 * 16];
+  __shared__ double red[11 * 16];
   float* sm = reinterpret_cast<float*>(lds_raw);
   cpx<float>* ph = reinterpret_cast<cpx<float>*>(lds_raw + SL::data_bytes);
   const int cell = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -780,7 +786,7 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
   // sums over x are taken first, then weighted by v_y (and v_z once at the end).
   float* oc = out + size_t(cell) * N * N * N;
   const double dv = 2.0 * L / N;
-  double s0 = 0, sx = 0, sy = 0, s2 = 0, a0 = 0, ax = 0, ay = 0, a2 = 0;
+  double s0 = 0, sx = 0, sy = 0, s2 = 0, a0 = 0, ax = 0, ay = 0, a2 = 0, qq = 0;
   for (int line = tid; line < N * N; line += nt) {
     const int y = line / N, z = line % N;
     const int base = y * RS + z;
@@ -792,6 +798,7 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
       double l0 = 0, l1 = 0, l2 = 0, b0 = 0, b1 = 0, b2 = 0;
       static_for<0, N>([&](auto j) {
         const double vx = -L + decltype(j)::value * dv, d = double(r[j]), ad = fabs(d);
+        qq += d * d;
         l0 += d;
         l1 += vx * d;
         l2 += vx * vx * d;
@@ -812,12 +819,13 @@ __global__ __launch_bounds__(512) void k_shift(const float* __restrict__ in, int
   }
   if (r_out) {
     const double vz = -L + (tid % N) * dv;
-    double acc[10] = {s0, sx, sy, vz * s0, 0.5 * (s2 + vz * vz * s0),
-                      a0, ax, ay, fabs(vz) * a0, 0.5 * (a2 + vz * vz * a0)};
-    block_sum10(acc, red);
+    double acc[11] = {s0, sx, sy, vz * s0, 0.5 * (s2 + vz * vz * s0),
+                      a0, ax, ay, fabs(vz) * a0, 0.5 * (a2 + vz * vz * a0), qq};
+    block_sum11(acc, red);
     if (tid == 0) {
       double rr = 0.0;
       for (int k = 0; k < 5; ++k) rr = fmax(rr, fabs(acc[k]) / (acc[5 + k] + 1e-300));
+      if (absolute) rr *= sqrt(acc[10]);
       r_out[cell] = rr;
     }
   }
@@ -1012,9 +1020,9 @@ hipError_t launch_lowmodes(int dtype_is_f32, const void* fhat, int rows, int hal
 }
 
 hipError_t launch_sur_output(const float* Y, int ldy, const float* rho, float scale, int n, double L, float* q,
-                             double* r, int64_t cells, void* stream) {
+                             double* r, int absolute, int64_t cells, void* stream) {
   hipLaunchKernelGGL(k_sur_output, dim3(unsigned(cells)), dim3(256), 0, static_cast<hipStream_t>(stream), Y, ldy, rho,
-                     scale, n, L, q, r);
+                     scale, n, L, q, r, absolute);
   return hipGetLastError();
 }
 
@@ -1034,7 +1042,8 @@ hipError_t launch_sur_target(const float* q, const float* rho, float inv_scale, 
 
 template <int N>
 static hipError_t launch_shift_n(const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
-                                 const float* rho, float scale, int mode, double* r, int64_t cells, hipStream_t st) {
+                                 const float* rho, float scale, int mode, double* r, int absolute, int64_t cells,
+                                 hipStream_t st) {
   static bool attr_set = false;
   constexpr size_t lds = ShiftLds<N>::bytes;
   if (!attr_set) {
@@ -1044,18 +1053,19 @@ static hipError_t launch_shift_n(const float* in, int64_t ld_in, float* out, con
     attr_set = true;
   }
   hipLaunchKernelGGL((k_shift<N>), dim3(unsigned(cells)), dim3(ShiftLds<N>::TPB), lds, st, in, ld_in, out, mom, sign,
-                     L, rho, scale, mode, r);
+                     L, rho, scale, mode, r, absolute);
   return hipGetLastError();
 }
 
 hipError_t launch_shift(int n, const float* in, int64_t ld_in, float* out, const double* mom, int sign, double L,
-                        const float* rho, float scale, int mode, double* r, int64_t cells, void* stream) {
+                        const float* rho, float scale, int mode, double* r, int absolute, int64_t cells,
+                        void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (n) {
-    case 8: return launch_shift_n<8>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
-    case 16: return launch_shift_n<16>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
-    case 24: return launch_shift_n<24>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
-    case 32: return launch_shift_n<32>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, cells, st);
+    case 8: return launch_shift_n<8>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, absolute, cells, st);
+    case 16: return launch_shift_n<16>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, absolute, cells, st);
+    case 24: return launch_shift_n<24>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, absolute, cells, st);
+    case 32: return launch_shift_n<32>(in, ld_in, out, mom, sign, L, rho, scale, mode, r, absolute, cells, st);
     default: return hipErrorInvalidValue;
   }
 }

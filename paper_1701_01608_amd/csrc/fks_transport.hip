@@ -432,6 +432,79 @@ __global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES
   }
 }
 
+// Normalised non-equilibrium residual of each cell's f (the macroscopic moments of
+// Section 3 one order further): with rho, u, T of f, the deviatoric stress
+// sigma_ij = sum f c_i c_j dv^3 - rho T delta_ij and the heat flux q_i = 1/2 sum f |c|^2 c_i dv^3
+// (c = v - u) vanish for a Maxwellian; r = |sigma|_F / (rho T) + |q| / (rho T^{3/2}).  One
+// workgroup per cell, FP64 sums of the raw moments (1, v, v v, |v|^2 v) in one pass, the
+// central ones formed from them.
+__global__ __launch_bounds__(256) void k_noneq(const void* __restrict__ fv, int is_f32, int n, double L,
+                                               double* __restrict__ r_out) {
+  __shared__ double red[13 * 4];
+  const int cell = blockIdx.x, nv = n * n * n, tid = threadIdx.x;
+  const double dv = 2.0 * L / n;
+  double m[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // 1, v(3), vv(6: xx yy zz xy xz yz), |v|^2 v(3)
+  for (int k = tid; k < nv; k += blockDim.x) {
+    const double x = is_f32 ? double(static_cast<const float*>(fv)[size_t(cell) * nv + k])
+                            : static_cast<const double*>(fv)[size_t(cell) * nv + k];
+    const double vx = -L + double(k / (n * n)) * dv, vy = -L + double((k / n) % n) * dv, vz = -L + double(k % n) * dv;
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    m[0] += x;
+    m[1] += x * vx;
+    m[2] += x * vy;
+    m[3] += x * vz;
+    m[4] += x * vx * vx;
+    m[5] += x * vy * vy;
+    m[6] += x * vz * vz;
+    m[7] += x * vx * vy;
+    m[8] += x * vx * vz;
+    m[9] += x * vy * vz;
+    m[10] += x * v2 * vx;
+    m[11] += x * v2 * vy;
+    m[12] += x * v2 * vz;
+  }
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int i = 0; i < 13; ++i) {
+    double v = m[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[i * 4 + wid] = v;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  const double w = dv * dv * dv;
+  double M[13];
+  for (int i = 0; i < 13; ++i) M[i] = w * (red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3]);
+  const double rho = M[0];
+  const double u[3] = {M[1] / rho, M[2] / rho, M[3] / rho};
+  const double M2[3][3] = {{M[4], M[7], M[8]}, {M[7], M[5], M[9]}, {M[8], M[9], M[6]}};
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = M2[i][j] - rho * u[i] * u[j];
+  const double T = (P[0][0] + P[1][1] + P[2][2]) / (3.0 * rho);
+  double s2 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double sg = P[i][j] - (i == j ? rho * T : 0.0);
+      s2 += sg * sg;
+    }
+  // sum f |c|^2 c_i = M3_i - u_i tr(M2) - 2 (M2 u)_i + 2 rho |u|^2 u_i
+  const double tr = M[4] + M[5] + M[6], uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double q2 = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const double mu = M2[i][0] * u[0] + M2[i][1] * u[1] + M2[i][2] * u[2];
+    const double qi = 0.5 * (M[10 + i] - u[i] * tr - 2.0 * mu + 2.0 * rho * uu * u[i]);
+    q2 += qi * qi;
+  }
+  r_out[cell] = sqrt(s2) / (rho * T) + sqrt(q2) / (rho * T * sqrt(T));
+}
+
+hipError_t launch_noneq(int dtype_is_f32, int n, const void* f, int64_t cells, double L, double* r, void* stream) {
+  if (cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_noneq, dim3(unsigned(cells)), dim3(256), 0, static_cast<hipStream_t>(stream), f,
+                     dtype_is_f32, n, L, r);
+  return hipGetLastError();
+}
+
 // ToPrimitive of [cells][5] conservative variables (in may equal out)
 __global__ void k_to_primitive(const double* in, double* out, int64_t cells) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -191,6 +191,48 @@ def test_infer_indicator_and_fallback():
     assert torch.equal(q_all, q_spec)
 
 
+@pytest.mark.parametrize("center", [False, True])
+def test_ranked_fallback(center):
+    # the absolute residual a = r ||Q_sur||_2 ranks the cells; per chunk the ceil(frac c)
+    # largest fall back to the spectral Q (bit for bit), the others keep the surrogate's Q
+    import paper_1701_01608_amd as fks
+    from fks_inputs import perturbed_maxwellians
+    from oracle import mlp
+    n, L, cells, mb = 16, 8.0, 300, 128                       # three chunks: 128, 128, 44
+    f = perturbed_maxwellians(n, L, cells, seed=4)
+    plan = fks.Plan(n=n, L=L, R=6.0, a1=4, a2=4, dtype="f32", max_cells=64)
+    sur = fks.Surrogate(n=n, modes=8, width=128, max_batch=mb, center=center)
+    sur.set_params(mlp.init_params([sur.n_in, 128, 128, sur.n_out], 11))
+    fd = torch.as_tensor(f, dtype=torch.float32).cuda().contiguous()
+    q_spec = plan.collide(fd)
+    r = torch.empty(cells, dtype=torch.float64, device="cuda")
+    a = torch.empty(cells, dtype=torch.float64, device="cuda")
+    q_sur, nf0 = sur.infer(plan, fd, threshold=-1.0, indicator=r)
+    q_sur2, nf1 = sur.infer_ranked(plan, fd, 0.0, indicator=a)
+    torch.cuda.synchronize()
+    assert nf0 == 0 and nf1 == 0 and torch.equal(q_sur, q_sur2)
+    expect = r * q_sur.double().flatten(1).norm(dim=1)
+    assert torch.allclose(a, expect, rtol=1e-12, atol=0.0)
+    frac = 0.3
+    q_h, nf = sur.infer_ranked(plan, fd, frac)
+    torch.cuda.synchronize()
+    fell = np.zeros(cells, dtype=bool)
+    an = a.cpu().numpy()
+    for c0 in range(0, cells, mb):
+        c = min(mb, cells - c0)
+        k = int(np.ceil(frac * c))
+        top = np.argsort(-an[c0:c0 + c])[:k]
+        fell[c0 + top] = True
+    assert nf == int(fell.sum())
+    m = torch.as_tensor(fell, device="cuda")
+    assert torch.equal(q_h[m], q_spec[m]) and torch.equal(q_h[~m], q_sur[~m])
+    # all and nothing
+    q_all, nf = sur.infer_ranked(plan, fd, 1.0)
+    assert nf == cells and torch.equal(q_all, q_spec)
+    with pytest.raises(fks.FKSError):
+        sur.infer_ranked(plan, fd, 1.5)
+
+
 def test_centred_targets_and_inference_match_oracle():
     """Centred surrogate: targets are Q(v + u) / (s rho^2) and predictions s rho^2 y(v - u),
     both by the exact spectral shift; checked against the oracle's shift of the GPU's own
@@ -383,3 +425,15 @@ def test_trained_surrogate_gain_over_spectral_path():
           f"spectral {t_spec * 1e3:.3f} ms ({t_spec / t_sur:.1f}x)")
     assert e1 < 0.5 and e1 < 0.5 * e0
     assert t_spec > 3.0 * t_sur
+    # at an equal fallback share (half the cells), ranking the cells by the absolute
+    # residual r ||Q_sur|| leaves a smaller batch error than a threshold on the relative
+    # residual r: the batch rel-L2 is carried by the cells with the largest Q
+    r = torch.empty(cells, dtype=torch.float64, device="cuda")
+    sur.infer(plan, f_val, threshold=-1.0, indicator=r)
+    thr = float(torch.quantile(r, 0.5))
+    q_rel, n_rel = sur.infer(plan, f_val, threshold=thr)
+    q_abs, n_abs = sur.infer_ranked(plan, f_val, n_rel / cells)
+    e_rel = float((q_rel - q_spec).double().norm() / q_spec.double().norm())
+    e_abs = float((q_abs - q_spec).double().norm() / q_spec.double().norm())
+    print(f"fallback {n_rel} cells: relative-threshold {e_rel:.3e}, ranked absolute {e_abs:.3e}")
+    assert abs(n_abs - n_rel) <= 1 and e_abs < e_rel < e1
