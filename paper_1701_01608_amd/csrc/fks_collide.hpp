@@ -274,6 +274,84 @@ __global__ __launch_bounds__(512) void k_forward_lds(const T* __restrict__ f, cp
   for (int i = tid; i < (C::NRL - N) * NPAIR; i += nt) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
 }
 
+// Forward transform in two k_z passes for cells whose partial spectra exceed the LDS (FP64
+// n = 32): pass p reduces the real z rows to the modes k_z = p KB .. p KB + KB - 1 of
+// 0..N/2-1, runs the y and x passes on them in LDS and writes their pencils; f is read once
+// per pass (the second time mostly from the caches), fhat written once.
+template <typename T, int N>
+struct FwdSplit {
+  static constexpr int KH1 = N / 2;
+  static constexpr int KB = KH1 / 2;
+  static constexpr int RS = KB + 1;
+  static constexpr size_t bytes = size_t(N) * N * RS * sizeof(cpx<T>);
+  static constexpr bool fits = bytes <= 156 * 1024;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_forward_split(const T* __restrict__ f, cpx<T>* __restrict__ fhat) {
+  using C = Grid<T, N>;
+  using F = FwdSplit<T, N>;
+  constexpr int K = C::K, Kh = C::Kh, KH1 = F::KH1, KB = F::KB, RS = F::RS, NPAIR = C::NPAIR, H = N / 2;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cpx<T>* sm = reinterpret_cast<cpx<T>*>(lds_raw);
+  const int cell = blockIdx.x;
+  const T* fc = f + size_t(cell) * N * N * N;
+  cpx<T>* fh = fhat + size_t(cell) * C::NRL * NPAIR;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr T scale = T(1.0 / (double(N) * N * N));
+  static_for<0, 2>([&](auto pc) {
+    constexpr int kz0 = decltype(pc)::value * KB;
+    // z pass: real rows (x, y) -> the pass's KB modes
+    for (int it = tid; it < N * N; it += nt) {
+      T r[N];
+      const T* row = fc + size_t(it) * N;
+      static_for<0, N>([&](auto z) { r[z] = row[z]; });
+      cpx<T> o[KH1];
+      rdft_low<N, KH1>(r, o);
+      static_for<0, KB>([&](auto j) { sm[size_t(it) * RS + j] = o[kz0 + decltype(j)::value]; });
+    }
+    __syncthreads();
+    // y pass: columns (x, j), in place y -> k_y index k_y + Kh
+    for (int it = tid; it < N * KB; it += nt) {
+      const int x = it / KB, j = it % KB;
+      cpx<T> a[N];
+      static_for<0, N>([&](auto y) { a[y] = sm[(size_t(x) * N + y) * RS + j]; });
+      dft<N, -1>(a);
+      static_for<0, K>([&](auto kyi) {
+        sm[(size_t(x) * N + kyi) * RS + j] = a[(decltype(kyi)::value - Kh + N) % N];
+      });
+    }
+    __syncthreads();
+    // x pass: lines (k_y, k_z) as in the LDS-resident kernel
+    for (int it = tid; it < KB * K; it += nt) {
+      const int j = it / K, kyi = it % K;
+      const int kz = kz0 + j, ky = kyi - Kh;
+      cpx<T> a[N];
+      static_for<0, N>([&](auto x) { a[x] = sm[(size_t(x) * N + kyi) * RS + j]; });
+      dft<N, -1>(a);
+      static_for<0, K>([&](auto kxi) {
+        constexpr int kx = decltype(kxi)::value - Kh;
+        const cpx<T> v = a[(kx + N) % N];
+        const cpx<T> sv = {v.re * scale, v.im * scale};
+        const bool direct = kx > 0 || (kx == 0 && ky >= 0);
+        if (direct) {
+          const int p = kx > 0 ? (kx - 1) * K + kyi : Kh * K + ky;
+          fh[size_t(kz + H) * NPAIR + p] = sv;
+          if (kx == 0 && ky == 0 && kz > 0) fh[size_t(H - kz) * NPAIR + p] = conj(sv);
+        } else if (kz > 0) {
+          const int mkx = -kx, mky = -ky;
+          const int p = mkx > 0 ? (mkx - 1) * K + (mky + Kh) : Kh * K + mky;
+          fh[size_t(H - kz) * NPAIR + p] = conj(sv);
+        }
+      });
+    }
+    __syncthreads();  // the next pass overwrites the LDS
+  });
+  for (int i = tid; i < NPAIR; i += nt) fh[i] = cpx<T>{T(0), T(0)};
+  for (int i = tid; i < (C::NRL - N) * NPAIR; i += nt) fh[size_t(N) * NPAIR + i] = cpx<T>{T(0), T(0)};
+}
+
+
 // ------------------------------------------------------------------------------------
 // kernel 2: one slab of one cell, all separable terms
 template <typename T, int N, int S, int RID>
@@ -837,6 +915,112 @@ __global__ __launch_bounds__(512) void k_finish_lds(const cpx<T>* __restrict__ D
   }
 }
 
+// Finish in two z passes for cells whose kept spectrum exceeds the LDS (FP64 n = 32),
+// without the conservation projection (which needs Q's moments before any output):
+// pass p combines the slab partials and synthesises along z (keeping the pass's N/2
+// planes), then along y and x in LDS, and writes Q, the Euler update and the moments'
+// share of its planes.  The slab partials are read once per pass.
+template <typename T, int N>
+struct FinSplit {
+  static constexpr int KH1 = N / 2;
+  static constexpr int ZB = N / 2;
+  static constexpr int RS = ZB + 1;
+  static constexpr size_t bytes = size_t(KH1) * N * RS * sizeof(cpx<T>);
+  static constexpr bool fits = bytes <= 156 * 1024;
+};
+
+template <typename T, int N, int S_>
+__global__ __launch_bounds__(256) void k_finish_split(const cpx<T>* __restrict__ D, int tg, const T* f_in, T* q,
+                                                      T* f_out, double dt, double* __restrict__ moments,
+                                                      EpiParams ep) {
+  using C = Cfg<T, N, S_>;
+  using F = FinSplit<T, N>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, Z = C::Z, S = C::S, RS = F::RS, ZB = F::ZB;
+  static_assert(KH1 == F::KH1, "half spectrum size");
+  constexpr size_t N3 = size_t(N) * N * N;
+  __shared__ double red[5 * 16];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cpx<T>* sm = reinterpret_cast<cpx<T>*>(lds_raw);
+  const int cell = blockIdx.x;
+  constexpr size_t DS = size_t(KH1) * K * Z;
+  const cpx<T>* Dc = D + size_t(cell) * tg * S * DS;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr double inv_p3 = 1.0 / (double(P) * P * P);
+  const T* fi = f_in ? f_in + size_t(cell) * N3 : nullptr;
+  T* qo = q ? q + size_t(cell) * N3 : nullptr;
+  T* fo = f_out ? f_out + size_t(cell) * N3 : nullptr;
+  double u[5] = {0, 0, 0, 0, 0};
+  static_for<0, 2>([&](auto pc) {
+    constexpr int z0 = decltype(pc)::value * ZB;
+    for (int it = tid; it < KH1 * K; it += nt) {
+      const int kx = it / K, kyi = it % K;
+      cpx<T> a[N];
+      static_for<0, N>([&](auto z) { a[z] = cpx<T>{T(0), T(0)}; });
+      static_for<0, K>([&](auto kzi) {
+        constexpr int kz = decltype(kzi)::value - Kh;
+        constexpr int b = ((kz % Z) + Z) % Z;
+        cpx<T> acc = {T(0), T(0)};
+        static_for<0, S>([&](auto r) {
+          const cpx<T> d = Dc[size_t(decltype(r)::value) * DS + size_t(it) * Z + b];
+          acc = acc + twiddle<P, -1, long(kz) * decltype(r)::value>(d);
+        });
+        a[(kz + N) % N] = cpx<T>{T(acc.re * T(inv_p3)), T(acc.im * T(inv_p3))};
+      });
+      dft<N, +1>(a);
+      static_for<0, ZB>([&](auto zl) { sm[(size_t(kx) * N + kyi) * RS + zl] = a[z0 + decltype(zl)::value]; });
+    }
+    __syncthreads();
+    // y synthesis: columns (kx, z of the pass), in place ky -> y
+    for (int it = tid; it < KH1 * ZB; it += nt) {
+      const int kx = it / ZB, zl = it % ZB;
+      cpx<T> a[N];
+      static_for<0, N>([&](auto y) { a[y] = cpx<T>{T(0), T(0)}; });
+      static_for<0, K>([&](auto kyi) {
+        a[(decltype(kyi)::value - Kh + N) % N] = sm[(size_t(kx) * N + kyi) * RS + zl];
+      });
+      dft<N, +1>(a);
+      static_for<0, N>([&](auto y) { sm[(size_t(kx) * N + y) * RS + zl] = a[y]; });
+    }
+    __syncthreads();
+    // x synthesis (Hermitian in kx) -> real Q of the pass's planes, written out
+    for (int it = tid; it < N * ZB; it += nt) {
+      const int y = it / ZB, zl = it % ZB, z = z0 + zl;
+      cpx<T> a[N];
+      static_for<0, N>([&](auto x) { a[x] = cpx<T>{T(0), T(0)}; });
+      static_for<0, KH1>([&](auto kx) {
+        const cpx<T> v = sm[(size_t(decltype(kx)::value) * N + y) * RS + zl];
+        a[kx] = v;
+        if constexpr (decltype(kx)::value > 0) a[N - decltype(kx)::value] = conj(v);
+      });
+      dft<N, +1>(a);
+      const double vy = -ep.L + y * ep.dv, vz = -ep.L + z * ep.dv;
+      static_for<0, N>([&](auto x) {
+        const size_t i = (size_t(decltype(x)::value) * N + y) * N + z;
+        const T qv = a[x].re;
+        if (qo) qo[i] = qv;
+        if (fo) {
+          const T nv = T(double(fi[i]) + dt * double(qv));
+          fo[i] = nv;
+          const double d = double(nv), vx = -ep.L + decltype(x)::value * ep.dv;
+          u[0] += d;
+          u[1] += vx * d;
+          u[2] += vy * d;
+          u[3] += vz * d;
+          u[4] += 0.5 * (vx * vx + vy * vy + vz * vz) * d;
+        }
+      });
+    }
+    __syncthreads();  // the next pass overwrites the LDS
+  });
+  if (moments && fo) {
+    block_reduce5(u, red);
+    if (tid == 0) {
+      const double w = ep.dv * ep.dv * ep.dv;
+      for (int i = 0; i < 5; ++i) moments[size_t(cell) * 5 + i] = u[i] * w;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // FP64 moments of f: dv^3 sum phi(v) f
 template <typename T, int N>
@@ -895,6 +1079,17 @@ static hipError_t launch_forward_kernel(const T* f, cpx<T>* fhat, cpx<T>* scr, i
     (void)scr;
     constexpr size_t lds = FwdLds<T, N>::bytes;
     hipLaunchKernelGGL((k_forward_lds<T, N>), dim3(cells), dim3(512), lds, st, f, fhat);
+  } else if constexpr (FwdSplit<T, N>::fits) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_split<T, N>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               int(FwdSplit<T, N>::bytes));
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    (void)scr;
+    hipLaunchKernelGGL((k_forward_split<T, N>), dim3(cells), dim3(512), (FwdSplit<T, N>::bytes), st, f, fhat);
   } else {
     hipLaunchKernelGGL((k_forward_f<T, N>), dim3(cells), dim3(256), 0, st, f, fhat, scr);
   }
@@ -947,9 +1142,28 @@ static hipError_t launch_collide_sched(const CollideArgs& a) {
                        static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
                        a.moments, a.ep);
   } else {
-    hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, tg, scr,
-                       static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
-                       a.moments, a.ep);
+    bool split = false;
+    if constexpr (FinSplit<T, N>::fits) {
+      // without the conservation projection the cell's Q can be written plane by plane
+      if (!a.ep.conserve) {
+        static bool fin_attr_set = false;
+        if (!fin_attr_set) {
+          const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_finish_split<T, N, S>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   int(FinSplit<T, N>::bytes));
+          if (e != hipSuccess) return e;
+          fin_attr_set = true;
+        }
+        hipLaunchKernelGGL((k_finish_split<T, N, S>), dim3(cells), dim3(256), (FinSplit<T, N>::bytes), st, D, tg,
+                           static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
+                           a.moments, a.ep);
+        split = true;
+      }
+    }
+    if (!split)
+      hipLaunchKernelGGL((k_finish<T, N, S>), dim3(cells), dim3(256), 0, st, D, tg, scr,
+                         static_cast<const T*>(a.f_in), static_cast<T*>(a.q), static_cast<T*>(a.f_out), a.dt,
+                         a.moments, a.ep);
   }
   prof_mark(kProfFinish, false, st);
   return hipGetLastError();
