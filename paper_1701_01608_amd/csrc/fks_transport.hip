@@ -63,8 +63,9 @@ __device__ __forceinline__ int wrap_sub(int c, int d, int m) {
 // One transport step per cell, with the macroscopic variables of the FKS step (Section 3
 // eq. DM_update, Section 4.1 sequential algorithm) and the BGK relaxation (Section 2.2.1),
 // in one kernel: one workgroup per destination cell j, streaming the cell's shifted
-// masses f*[j][k] = f[j - delta_k][k] in batches (a second time for the relaxation, after
-// the per-cell setup, mostly from L2).
+// masses f*[j][k] = f[j - delta_k][k] in batches (for the relaxation after the per-cell
+// setup, a cell of at most 64 KB reads them back from LDS, a larger one streams them a
+// second time, mostly from L2).
 //   MODE 3  shift only: f_out = f*.
 //   MODE 0  shift and eq. DM_update: for every velocity k that moved this step
 //           (delta_k != 0) the sister particle from cell j - delta_k replaces the one that
@@ -216,6 +217,11 @@ __global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES
   using CS = CellShape<T, N>;
   constexpr int NV = CS::NV, NTH = CS::NTH, VPT = CS::VPT;
   constexpr bool DM = MODE != 3, BGK = MODE == 1 || MODE == 2;
+  // cells of at most 64 KB keep their shifted masses in LDS between the two passes (each
+  // thread reads back what it wrote); larger ones stream them a second time from the caches
+  constexpr bool STAGE = BGK && CS::NV * sizeof(T) <= 64 * 1024;
+  extern __shared__ __align__(16) unsigned char stage_raw[];
+  T* stage = reinterpret_cast<T*>(stage_raw);
   // the Maxwellian and the relaxation are evaluated in the storage precision (FP32 cells:
   // a few FP32 roundings, far below the rounding of the stored result's neighbours; FP64:
   // FP64); the sums of DM_update and the optional moments are FP64
@@ -269,8 +275,9 @@ __global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES
       }
     };
     // The values stream in batches of B (the loads of a batch are all issued before any is
-    // used); the relaxation streams the shifted masses a second time after the per-cell
-    // setup (from L2 or the last-level cache) instead of holding them in registers across it.
+    // used); after the per-cell setup the relaxation reads the shifted masses back from LDS
+    // (STAGE) or streams them a second time from the caches, instead of holding them in
+    // registers across the setup.
     constexpr int B = CS::B;
     const double vz = -a.L + double(iz) * dv;
     // eq. DM_update: the sister particle of every moved velocity.  The own-cell value is
@@ -290,6 +297,10 @@ __global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES
       for (int j = 0; j < B; ++j) {
         xs[j] = load_shifted(u0 + j);
         if constexpr (DM) vo[j] = fown[uint32_t((u0 + j) * NTH + tcell)];
+      }
+      if constexpr (STAGE) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) stage[(u0 + j) * NTH + tcell] = xs[j];
       }
       if constexpr (!BGK) {
 #pragma unroll
@@ -398,7 +409,7 @@ __global__ __launch_bounds__((CellShape<T, N>::NTH), (CellShape<T, N>::MIN_WAVES
       for (int u0 = 0; u0 < VPT; u0 += B) {
         T xs[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) xs[j] = load_shifted(u0 + j);
+        for (int j = 0; j < B; ++j) xs[j] = STAGE ? stage[(u0 + j) * NTH + tcell] : load_shifted(u0 + j);
 #pragma unroll
         for (int j = 0; j < B; ++j) {
           const int h = j % H, ix = ((u0 + j) / H) * MM + ix0, k = (u0 + j) * NTH + tcell;
@@ -554,15 +565,18 @@ static hipError_t launch_cell_step(int dtype_is_f32, const void* fin, void* fout
     const T* fi = static_cast<const T*>(fin);
     T* fo = static_cast<T*>(fout);
     const bool extras = a.q || a.moments;
+    // LDS for the BGK modes' staged masses (see STAGE in the kernel)
+    constexpr size_t cb = size_t(CellShape<T, NN>::NV) * sizeof(T);
+    constexpr size_t sl = cb <= 64 * 1024 ? cb : 0;
     switch (mode) {
       case 0: hipLaunchKernelGGL((k_cell_step<T, NN, 0, false>), grid, block, 0, st, fi, fo, d1, a); break;
       case 1:
-        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 1, true>), grid, block, 0, st, fi, fo, d1, a);
-        else hipLaunchKernelGGL((k_cell_step<T, NN, 1, false>), grid, block, 0, st, fi, fo, d1, a);
+        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 1, true>), grid, block, sl, st, fi, fo, d1, a);
+        else hipLaunchKernelGGL((k_cell_step<T, NN, 1, false>), grid, block, sl, st, fi, fo, d1, a);
         break;
       case 2:
-        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 2, true>), grid, block, 0, st, fi, fo, d1, a);
-        else hipLaunchKernelGGL((k_cell_step<T, NN, 2, false>), grid, block, 0, st, fi, fo, d1, a);
+        if (extras) hipLaunchKernelGGL((k_cell_step<T, NN, 2, true>), grid, block, sl, st, fi, fo, d1, a);
+        else hipLaunchKernelGGL((k_cell_step<T, NN, 2, false>), grid, block, sl, st, fi, fo, d1, a);
         break;
       case 3: hipLaunchKernelGGL((k_cell_step<T, NN, 3, false>), grid, block, 0, st, fi, fo, d1, a); break;
       default: return hipErrorInvalidValue;
