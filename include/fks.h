@@ -186,7 +186,8 @@ fks_status fks_plan_autotune(fks_plan plan, const void* f, void* q, int64_t n_ce
 /* ---- transport (Section 2.1 transport step; Section 3 generic cell) -------------- */
 
 /* Periodic box of nx*ny*nz cells of width dx (cells in C order [nx][ny][nz], at most
- * 2^24) for the velocity grid (n, L), n in {8, 12, 16, 24, 32} (else FKS_E_UNSUPPORTED).
+ * 2^24, and ny*nz*n^3 < 2^31) for the velocity grid (n, L), n in {8, 12, 16, 24, 32} (else
+ * FKS_E_UNSUPPORTED).
  * Each velocity k keeps an FP64 sub-cell offset s_k and an integer cumulative shift o_k
  * (device state, caller-owned). */
 fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t nz, double dx,

@@ -1427,6 +1427,9 @@ fks_status fks_xport_create(int32_t n, double L, int32_t nx, int32_t ny, int32_t
     return fail(FKS_E_UNSUPPORTED, "transport velocity grids: n in {8, 12, 16, 24, 32}, got %d", n);
   if (nx < 1 || ny < 1 || nz < 1) return fail(FKS_E_ARG, "box sizes must be >= 1");
   if (int64_t(nx) * ny * nz > (int64_t(1) << 24)) return fail(FKS_E_ARG, "too many cells");
+  // the per-cell kernels address a y-z plane of the box with 32-bit offsets
+  if (int64_t(ny) * nz * int64_t(n) * n * n >= (int64_t(1) << 31))
+    return fail(FKS_E_UNSUPPORTED, "a y-z plane of the box must hold fewer than 2^31 values (ny nz n^3)");
   if (!(L > 0.0) || !(dx > 0.0) || !std::isfinite(L) || !std::isfinite(dx))
     return fail(FKS_E_ARG, "L and dx must be positive");
   fks_xport_s* x = new (std::nothrow) fks_xport_s();

@@ -109,6 +109,7 @@ def test_transport_create_validation(lib):
     assert L.fks_xport_create(16, 8.0, 4, 4, 4, -0.1, ctypes.byref(h)) == -1
     assert L.fks_xport_create(20, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) == L.fks_xport_create(64, 8.0, 4, 4, 4, 0.1, ctypes.byref(h))
     assert L.fks_xport_create(20, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) < 0 and b"n in" in L.fks_last_error()
+    assert L.fks_xport_create(32, 8.0, 1, 256, 256, 0.1, ctypes.byref(h)) < 0 and b"y-z plane" in L.fks_last_error()
     assert L.fks_xport_create(16, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) == 0
     sb = ctypes.c_size_t()
     assert L.fks_xport_sizes(h, ctypes.byref(sb)) == 0 and sb.value >= 16 ** 3 * 48
