@@ -207,6 +207,18 @@ fks_status fks_xport_bind(fks_xport xp, void* d_state, size_t state_bytes, void*
 fks_status fks_transport(fks_xport xp, const void* f_in, void* f_out, int32_t dtype, double dt,
                          void* stream);
 
+/* fks_transport with the move of f optional.  materialize = 0: only the offsets advance
+ * (f_in, f_out unused, may be NULL); the integer shifts accumulate as pending in the state.
+ * materialize != 0: the offsets advance, then f_out[j][k] = f_in[(j - D_k) mod box][k] with
+ * D_k the shifts pending since f was last moved (this step's included), and the pending
+ * shifts are cleared.  Shifts are permutations of the cells per velocity, so several
+ * unmaterialised steps followed by one materialising call (dt = 0 adds no shift) give the
+ * same f as materialising every step.  fks_transport is materialize = 1; fks_step and
+ * fks_step_ex apply the pending shifts of earlier unmaterialised steps with their own
+ * (their eq. DM_update then counts the total displacement). */
+fks_status fks_transport_ex(fks_xport xp, const void* f_in, void* f_out, int32_t dtype, double dt,
+                            int32_t materialize, void* stream);
+
 /* n_steps split steps (eq. transport then eq. disc_relax) on the whole box:
  * f* = shift(f); f = f* + dt Q(f*).  f is updated in place; f_tmp is a caller buffer of
  * the same size.  d_moments (optional, [cells][5] FP64) receives the moments after the

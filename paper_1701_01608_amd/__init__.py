@@ -366,6 +366,21 @@ class Transport:
                                             _stream_ptr(stream)))
         return f_out
 
+    def advance(self, dt, stream=None):
+        """Advance the offsets by dt without moving f (the shifts stay pending)."""
+        _hold(self)
+        _lib.check(_lib.lib().fks_transport_ex(self._h, None, None, FKS_F32, float(dt), 0, _stream_ptr(stream)))
+
+    def materialize(self, f_in, f_out=None, stream=None):
+        """f_out = f_in moved by the shifts pending since f was last moved."""
+        if f_out is None:
+            f_out = _new_like(f_in, "f_out")
+        _hold(self, f_in, f_out)
+        code = FKS_F32 if f_in.dtype == torch.float32 else FKS_F64
+        _lib.check(_lib.lib().fks_transport_ex(self._h, _ptr(f_in), _ptr(f_out), code, 0.0, 1,
+                                               _stream_ptr(stream)))
+        return f_out
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib._lib is not None:

@@ -80,6 +80,7 @@ _SIGS = {
     "fks_xport_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "fks_xport_bind": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "fks_transport": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_double, _VP]),
+    "fks_transport_ex": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _VP]),
     "fks_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, _VP, _VP]),
     "fks_step_ex": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(StepOpts),
                                    _VP]),

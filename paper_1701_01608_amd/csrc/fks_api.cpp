@@ -1476,22 +1476,28 @@ fks_status fks_xport_bind(fks_xport x, void* d_state, size_t state_bytes, void* 
              : FKS_E_DEVICE;
 }
 
-fks_status fks_transport(fks_xport x, const void* f_in, void* f_out, int32_t dtype, double dt, void* stream) {
+fks_status fks_transport_ex(fks_xport x, const void* f_in, void* f_out, int32_t dtype, double dt,
+                            int32_t materialize, void* stream) {
   if (!x) return fail(FKS_E_ARG, "null transport");
   if (!x->bound) return fail(FKS_E_STATE, "transport state not bound");
-  if (!f_in || !f_out) return fail(FKS_E_ARG, "null f_in or f_out");
-  if (dtype != FKS_F32 && dtype != FKS_F64) return fail(FKS_E_ARG, "bad dtype");
   if (!std::isfinite(dt)) return fail(FKS_E_ARG, "dt must be finite");
   const int nv = x->n * x->n * x->n;
-  const size_t bytes = size_t(x->nx) * x->ny * x->nz * nv * (dtype == FKS_F32 ? 4 : 8);
-  if (ranges_overlap(f_in, f_out, bytes)) return fail(FKS_E_ARG, "f_out must not overlap f_in");
+  if (materialize) {
+    if (!f_in || !f_out) return fail(FKS_E_ARG, "null f_in or f_out");
+    if (dtype != FKS_F32 && dtype != FKS_F64) return fail(FKS_E_ARG, "bad dtype");
+    const size_t bytes = size_t(x->nx) * x->ny * x->nz * nv * (dtype == FKS_F32 ? 4 : 8);
+    if (ranges_overlap(f_in, f_out, bytes)) return fail(FKS_E_ARG, "f_out must not overlap f_in");
+  }
   const fks::XportState st = xport_state(x);
   fks_status s = check_hip(fks::launch_xport_advance(st, x->n, x->L, dt, x->dx, stream), "transport advance");
-  if (s != FKS_OK) return s;
+  if (s != FKS_OK || !materialize) return s == FKS_OK ? ok() : s;
   s = check_hip(fks::launch_roll(dtype == FKS_F32, f_in, f_out, st.d1, x->n, x->L, x->nx, x->ny, x->nz, stream),
                 "transport roll");
-  if (s != FKS_OK) return s;
-  return ok();
+  return s == FKS_OK ? ok() : s;
+}
+
+fks_status fks_transport(fks_xport x, const void* f_in, void* f_out, int32_t dtype, double dt, void* stream) {
+  return fks_transport_ex(x, f_in, f_out, dtype, dt, 1, stream);
 }
 
 fks_status fks_step(fks_plan p, fks_xport x, void* f, void* f_tmp, double dt, int32_t n_steps, double* d_moments,

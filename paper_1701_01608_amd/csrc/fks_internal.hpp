@@ -105,12 +105,14 @@ struct XportState {
   double* s;    // [nv][3] sub-cell offsets
   int32_t* o;   // [nv][3] cumulative integer shifts
   int32_t* dl;  // [nv][3] shift of the last step
-  int32_t* d1;  // [3][n] shift of the last step per axis and velocity index along that axis
+  int32_t* d1;  // [3][n] shift pending since f was last moved, per axis and index along it
 };
+hipError_t launch_clear_pending(int32_t* d1, int n, void* stream);
 hipError_t launch_xport_reset(const XportState& st, int n, void* stream);
 hipError_t launch_xport_advance(const XportState& st, int n, double L, double dt, double dx, void* stream);
-// f_out[j][k] = f_in[(j - delta_k) mod box][k] from the compact shift table
-hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int n, double L, int nx,
+// f_out[j][k] = f_in[(j - delta_k) mod box][k] with the pending shifts of the compact
+// table, which it then clears
+hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, int32_t* d1, int n, double L, int nx,
                        int ny, int nz, void* stream);
 
 // per-cell transport with eq. DM_update / ToPrimitive and optional BGK relaxation
@@ -129,7 +131,7 @@ struct StepCellArgs {
 // The shift from fin to fout with eq. DM_update of the conservative variables a.cons from
 // fin and this step's shifts (required); mode 0: nothing more; 1: BGK Euler and 2: BGK exact
 // relaxation of the shifted masses at the updated U
-hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
+hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, int32_t* d1, int mode,
                             const StepCellArgs& a, void* stream);
 hipError_t launch_to_primitive(const double* in, double* out, int64_t cells, void* stream);
 // normalised non-equilibrium residual (deviatoric stress, heat flux) per cell

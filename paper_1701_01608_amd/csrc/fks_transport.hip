@@ -25,8 +25,10 @@ __global__ void k_xport_reset(double* s, int32_t* o, int32_t* dl, int32_t* d1, i
 
 // The shift along axis a depends on the velocity's index along a only: every velocity
 // with the same component has the same offset history.  Besides the per-velocity state,
-// the velocities whose other two indices are zero write the step's shift of their axis
-// into the compact table d1[a][i] that the streaming kernels read.
+// the velocities whose other two indices are zero add the step's shift of their axis to
+// the compact table d1[a][i] of shifts pending since f was last moved; the streaming
+// kernels apply the pending shifts and k_clear_pending then zeroes them (steps that only
+// advance the offsets leave f in place and accumulate there).
 __global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int32_t* d1, int n, double L, double dt,
                                 double dx) {
 #pragma clang fp contract(off)
@@ -44,8 +46,13 @@ __global__ void k_xport_advance(double* s, int32_t* o, int32_t* dl, int32_t* d1,
     s[3 * k + a] = t - d * dx;
     dl[3 * k + a] = int32_t(d);
     o[3 * k + a] += int32_t(d);
-    if (idx[(a + 1) % 3] == 0 && idx[(a + 2) % 3] == 0) d1[a * n + idx[a]] = int32_t(d);
+    if (idx[(a + 1) % 3] == 0 && idx[(a + 2) % 3] == 0) d1[a * n + idx[a]] += int32_t(d);
   }
+}
+
+__global__ void k_clear_pending(int32_t* d1, int m1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m1) d1[i] = 0;
 }
 
 // (c - d) mod m for a shift d of at most one box length, without a division; larger shifts
@@ -548,6 +555,12 @@ hipError_t launch_xport_advance(const XportState& st, int n, double L, double dt
   return hipGetLastError();
 }
 
+hipError_t launch_clear_pending(int32_t* d1, int n, void* stream) {
+  hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(3 * n <= 1024 ? 3 * n : 1024), 0,
+                     static_cast<hipStream_t>(stream), d1, 3 * n);
+  return hipGetLastError();
+}
+
 // mode: 0 DM update + shift, 1 DM + Euler BGK, 2 DM + exact BGK, 3 shift only
 static hipError_t launch_cell_step(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
                                    const StepCellArgs& a, hipStream_t st) {
@@ -596,7 +609,7 @@ static hipError_t launch_cell_step(int dtype_is_f32, const void* fin, void* fout
   return dtype_is_f32 ? by_n(float{}) : by_n(double{});
 }
 
-hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int n, double L, int nx,
+hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, int32_t* d1, int n, double L, int nx,
                        int ny, int nz, void* stream) {
   StepCellArgs a{};
   a.n = n;
@@ -606,18 +619,20 @@ hipError_t launch_roll(int dtype_is_f32, const void* fin, void* fout, const int3
   a.nz = nz;
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_mark(kProfRoll, true, st);
-  const hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, 3, a, st);
+  hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, 3, a, st);
   prof_mark(kProfRoll, false, st);
+  if (e == hipSuccess) e = launch_clear_pending(d1, n, stream);
   return e;
 }
 
-hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, const int32_t* d1, int mode,
+hipError_t launch_step_cell(int dtype_is_f32, const void* fin, void* fout, int32_t* d1, int mode,
                             const StepCellArgs& a, void* stream) {
   if (mode < 0 || mode > 2) return hipErrorInvalidValue;
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_mark(kProfRoll, true, st);
-  const hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, mode, a, st);
+  hipError_t e = launch_cell_step(dtype_is_f32, fin, fout, d1, mode, a, st);
   prof_mark(kProfRoll, false, st);
+  if (e == hipSuccess) e = launch_clear_pending(d1, a.n, stream);
   return e;
 }
 

@@ -111,6 +111,9 @@ def test_transport_create_validation(lib):
     assert L.fks_xport_create(20, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) < 0 and b"n in" in L.fks_last_error()
     assert L.fks_xport_create(32, 8.0, 1, 256, 256, 0.1, ctypes.byref(h)) < 0 and b"y-z plane" in L.fks_last_error()
     assert L.fks_xport_create(16, 8.0, 4, 4, 4, 0.1, ctypes.byref(h)) == 0
+    # not bound yet: both modes of the deferred transport refuse
+    assert L.fks_transport_ex(h, None, None, 1, 0.01, 0, None) == -5
+    assert L.fks_transport_ex(h, None, None, 1, 0.01, 1, None) == -5
     sb = ctypes.c_size_t()
     assert L.fks_xport_sizes(h, ctypes.byref(sb)) == 0 and sb.value >= 16 ** 3 * 48
     assert L.fks_transport(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1, 0.1, None) == -5

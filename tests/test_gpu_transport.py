@@ -38,6 +38,64 @@ def test_transport_offsets_and_roll_bitwise():
     assert np.array_equal(cur.cpu().numpy().reshape(host.shape), host)
 
 
+@pytest.mark.parametrize("n", [8, 16])
+def test_deferred_transport_equals_stepwise(n):
+    # offsets advanced for several steps without moving f, then one materialising call:
+    # the same f (bit for bit) as moving f every step, and the oracle's composed shift;
+    # a Boltzmann step after unmaterialised steps applies the pending shifts with its own
+    from paper_1701_01608_amd import Transport
+    L, shape, dx, dt = 8.0, (4, 3, 5), 1.0 / 16, 0.004375
+    rng = np.random.default_rng(5)
+    f = torch.tensor(rng.random((np.prod(shape), n, n, n)), device="cuda")
+    xa, xb = Transport(n, L, shape, dx), Transport(n, L, shape, dx)
+    cur = f
+    for _ in range(7):
+        cur = xa(cur, dt=dt)                       # materialised every step
+    for _ in range(7):
+        xb.advance(dt)                             # offsets only
+    deferred = xb.materialize(f)
+    torch.cuda.synchronize()
+    assert torch.equal(deferred, cur)
+    vel = otr.velocity_table(n, L)
+    s = np.zeros_like(vel)
+    tot = np.zeros(vel.shape, dtype=np.int64)
+    for _ in range(7):
+        d, s = otr.advance(s, vel, dt, dx)
+        tot += d
+    host = otr.shift(f.cpu().numpy().reshape(len(f), -1), tot, shape)
+    assert np.array_equal(deferred.cpu().numpy().reshape(host.shape), host)
+    assert np.array_equal(xb.offsets()[1].cpu().numpy().astype(np.int64), tot)
+    # nothing pending after a materialisation: moving again with dt = 0 is the identity
+    again = xb.materialize(deferred)
+    torch.cuda.synchronize()
+    assert torch.equal(again, deferred)
+
+
+def test_deferred_shifts_enter_the_dm_update():
+    # two unmaterialised steps, then a Boltzmann step with eq. DM_update: the conservative
+    # variables equal the direct moments of the moved masses (the shift conserves them)
+    from paper_1701_01608_amd import Plan, Transport, step_ex
+    n, L, R, shape, dx, dt = 8, 8.0, 6.0, (5, 4, 3), 1.0 / 8, 0.02
+    f = torch.tensor(fks_inputs.maxwellian_mixture(n, L, int(np.prod(shape)), seed=8), device="cuda")
+    plan = Plan(n, L, R, dtype="f64", max_cells=64)
+    xp = Transport(n, L, shape, dx)
+    cons = plan.moments(f)
+    xp.advance(dt)
+    xp.advance(dt)
+    step_ex(plan, xp, f, 0.0, cons=cons)           # dt = 0: the pending shifts only, no collision change
+    torch.cuda.synchronize()
+    direct = plan.moments(f)
+    np.testing.assert_allclose(cons.cpu().numpy(), direct.cpu().numpy(), rtol=0,
+                               atol=1e-13 * direct.abs().max().item())
+    vel = otr.velocity_table(n, L)
+    s = np.zeros_like(vel)
+    tot = np.zeros(vel.shape, dtype=np.int64)
+    for _ in range(2):
+        d, s = otr.advance(s, vel, dt, dx)
+        tot += d
+    assert np.any(tot != 0)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_fks_step_small_box(dtype):
     from paper_1701_01608_amd import Plan, Transport, step
