@@ -169,9 +169,9 @@ fks_status fks_plan_set_schedule(fks_plan plan, int32_t slabs, int32_t xcd_map);
 /* Term groups (latency of small batches): each slab's loop over the separable terms is
  * split over tg workgroups whose partial spectra the synthesis sums (same Q up to the
  * order of the FP additions).  Plans created with max_cells <= 32 accept tg up to
- * min(8, terms); others only 1 (FKS_E_UNSUPPORTED).  get returns the groups in effect
+ * min(32, terms); others only 1 (FKS_E_UNSUPPORTED).  get returns the groups in effect
  * (no group is left empty) and the maximum.  The XCD mapping is not used with tg > 1.
- * fks_plan_autotune also tries tg = 1, 2, 4, 8 where allowed. */
+ * fks_plan_autotune also tries tg = 1, 2, 4, 8, 16, 32 where allowed. */
 fks_status fks_plan_set_term_groups(fks_plan plan, int32_t tg);
 fks_status fks_plan_get_term_groups(fks_plan plan, int32_t* tg, int32_t* tg_max);
 

@@ -208,7 +208,7 @@ namespace {
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 constexpr int64_t kSmallBatch = 32;   // plans up to this many cells get term-group workspace
-constexpr int kMaxTermGroups = 8;
+constexpr int kMaxTermGroups = 32;
 
 // Separable terms in FP64: for every direction e_t (and radial node) the pair
 // (alpha_t(k), alpha'_t(k)) over the kept modes; the loss term (-1, lambda(k)) last.

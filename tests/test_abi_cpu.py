@@ -154,13 +154,16 @@ def test_term_groups_limits(lib):
     assert st == 0
     tg, mx = ctypes.c_int32(), ctypes.c_int32()
     assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
-    assert (tg.value, mx.value) == (1, 8)
+    assert (tg.value, mx.value) == (1, 17)                   # at most one group per term
     assert L.fks_plan_set_term_groups(small, 0) == -1
-    assert L.fks_plan_set_term_groups(small, 9) == -2
+    assert L.fks_plan_set_term_groups(small, 18) == -2
     assert L.fks_plan_set_term_groups(small, 8) == 0
     # 17 terms in groups of ceil(17/8) = 3: 6 groups are used, none empty
     assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
     assert tg.value == 6
+    assert L.fks_plan_set_term_groups(small, 17) == 0
+    assert L.fks_plan_get_term_groups(small, ctypes.byref(tg), ctypes.byref(mx)) == 0
+    assert tg.value == 17
     L.fks_plan_destroy(small)
 
 
