@@ -286,7 +286,7 @@ def test_term_groups_match_oracle(dtype):
     ft = torch.tensor(f, dtype=torch.float32 if dtype == "f32" else torch.float64, device="cuda")
     ref, _ = oracle_q(ft.double().cpu().numpy(), n)
     q1 = plan.collide(ft).double().cpu().numpy()
-    for tg in (2, 3, 8):
+    for tg in (2, 3, 8, 17):                   # 17: one term per group
         plan.set_term_groups(tg)
         q = plan.collide(ft)
         torch.cuda.synchronize()
