@@ -837,13 +837,17 @@ fks_status fks_plan_get_term_groups(fks_plan p, int32_t* tg, int32_t* tg_max) {
 }
 
 namespace {
-std::string device_name() {
+// Writes the current device's architecture name without feature suffixes ("gfx950") into *out.
+void device_name(std::string* out) {
   int dev = 0;
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    *out = "unknown";
+    return;
+  }
   std::string a = prop.gcnArchName;
   const size_t c = a.find(':');
-  return c == std::string::npos ? a : a.substr(0, c);
+  *out = c == std::string::npos ? a : a.substr(0, c);
 }
 
 // cache line: {"device":"gfx950","n":32,"dtype":"f32","terms":17,"cells":4096,"slabs":6,"xcd":1,"ms":15.0}
@@ -874,9 +878,11 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
   if (s != FKS_OK) return s;
   if (!f || !q || n_cells < 1) return fail(FKS_E_ARG, "need f, q and n_cells >= 1");
   if (n_cells > p->max_cells) n_cells = p->max_cells;
+  std::string dev_name;
+  device_name(&dev_name);
   char keybuf[256];
   std::snprintf(keybuf, sizeof(keybuf), "\"device\":\"%s\",\"n\":%d,\"dtype\":\"%s\",\"terms\":%d,\"cells\":%lld",
-                device_name().c_str(), p->n, p->d.dtype == FKS_F32 ? "f32" : "f64", p->n_terms,
+                dev_name.c_str(), p->n, p->d.dtype == FKS_F32 ? "f32" : "f64", p->n_terms,
                 static_cast<long long>(n_cells));
   // the stored line continues with ',"slabs":', so matching the key plus its comma compares the
   // cell count exactly (4096 does not match a line written for 40960)
@@ -892,7 +898,7 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
   if (s != FKS_OK) return s;
   s = check_hip(hipEventCreate(&e1), "event");
   if (s != FKS_OK) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return s;
   }
   float best = 1e30f;
@@ -920,8 +926,8 @@ fks_status fks_plan_autotune(fks_plan p, const void* f, void* q, int64_t n_cells
           best_t = t;
         }
       }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   p->variant = best_v;
   p->xcd_map = best_x;
   p->tg = best_t;
@@ -1392,13 +1398,13 @@ fks_status fks_graph_end(void* stream, fks_graph* out) {
   hipGraphExec_t e = nullptr;
   s = check_hip(hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "graph instantiate");
   if (s != FKS_OK) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return s;
   }
   fks_graph_s* h = new (std::nothrow) fks_graph_s();
   if (!h) {
-    hipGraphExecDestroy(e);
-    hipGraphDestroy(g);
+    (void)hipGraphExecDestroy(e);
+    (void)hipGraphDestroy(g);
     return fail(FKS_E_ARG, "out of host memory");
   }
   h->graph = g;
@@ -1415,8 +1421,8 @@ fks_status fks_graph_launch(fks_graph g, void* stream) {
 
 void fks_graph_destroy(fks_graph g) {
   if (!g) return;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
 }
 

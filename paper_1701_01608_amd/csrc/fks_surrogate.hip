@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
                                               int N, int K, int lda, int ldb, const float* __restrict__ bias,
                                               float* __restrict__ Cf, __bf16* __restrict__ Ch,
                                               const float* __restrict__ Zin, int ldc, int k_split) {
+  (void)N;  // the grid covers N exactly: the launchers require N % GBN == 0
   // two LDS stages: the global loads of k tile i+1 are in flight (in registers) while
   // the matrix cores work on tile i
   __shared__ __align__(16) __bf16 As[2][GBM * GLD];
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(256) void k_gemm_big(const __bf16* __restrict__ A, 
                                                   int N, int K, int lda, int ldb, const float* __restrict__ bias,
                                                   float* __restrict__ Cf, __bf16* __restrict__ Ch,
                                                   const float* __restrict__ Zin, int ldc, int k_split) {
+  (void)N;  // the grid covers N exactly: the launchers require N % BBN == 0
   __shared__ __align__(16) __bf16 smem[2][(BBM + BBN) * GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * BBM, n0 = blockIdx.x * BBN;
@@ -885,6 +887,7 @@ __global__ __launch_bounds__(256) void k_scatter_cells(const T* __restrict__ src
 // launchers
 hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B, int M, int N, int K, int lda,
                        int ldb, const float* bias, float* Cf, void* Ch, const float* Zin, int ldc, void* stream) {
+  if (M % GBM || N % GBN || K % GBK) return hipErrorInvalidValue;
   const dim3 grid(N / GBN, M / GBM);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const __bf16* a = static_cast<const __bf16*>(A);
@@ -922,8 +925,10 @@ hipError_t launch_gemm(int a_km, int b_kn, int epi, const void* A, const void* B
 hipError_t launch_gemm_dsilu_splitk(const void* A, const void* B, int b_kn, int M, int N, int K, int lda, int ldb,
                                    const float* Zin, void* Ch, int splits, float* partial, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (splits < 1 || K % (splits * GBK)) return hipErrorInvalidValue;
   const int k_split = K / splits;
   if (b_kn) {
+    if (M % GBM || N % GBN) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gemm<false, true, kEpiPartial>), dim3(N / GBN, M / GBM, splits), dim3(256), 0, st,
                        static_cast<const __bf16*>(A), static_cast<const __bf16*>(B), M, N, K, lda, ldb,
                        static_cast<const float*>(nullptr), partial, static_cast<__bf16*>(nullptr), Zin, N, k_split);
