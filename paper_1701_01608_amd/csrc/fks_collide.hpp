@@ -89,9 +89,28 @@ struct Cfg : Grid<T, N> {
   // P-point line of doubles does not fit the registers of a 512-thread workgroup; FP32
   // keeps one thread per line)
   static constexpr bool FWD_PARTS = sizeof(T) == 8;
-  // one thread per line part and at least one per stage-1 pencil
+  // plain schedule: one thread per line part and at least one per stage-1 pencil
   static constexpr int NT_ = XP * LINES > NPAIR ? XP * LINES : NPAIR;
-  static constexpr int NT = (NT_ + 63) / 64 * 64;
+  static constexpr int NT_PLAIN = (NT_ + 63) / 64 * 64;
+  // Producer/consumer wave split (FP32): the first PW waves own the stage-1 pencils (f̂ kept
+  // in registers over all terms, one table load per row) and the stage-2 y lines; CT more
+  // threads own IPC stage-3 x-line parts each and their part of G, the x lines being taken
+  // in XP3 interleaved parts of P/XP3 outputs.  Used where the parts come in equal whole
+  // shares of at most three, each wave's parts lie in one part index (LINES a multiple of
+  // 64), and the workgroup stays within 1024 threads.
+  static constexpr int PW = ((NPAIR + 63) / 64 > (XP * Z * K + 63) / 64) ? (NPAIR + 63) / 64 : (XP * Z * K + 63) / 64;
+  static constexpr int XP3 = 4;
+  static constexpr int CT = 512;
+  static constexpr bool SPLIT = sizeof(T) == 4 && 64 * PW + CT <= 1024 && P % XP3 == 0 &&
+                                (XP3 * LINES) % CT == 0 && (XP3 * LINES) / CT <= 3 && LINES % 64 == 0;
+  static constexpr int IPC = SPLIT ? XP3 * LINES / CT : 0;
+  static constexpr int NT = SPLIT ? 64 * PW + CT : NT_PLAIN;
+  // table rows in flight per producer thread; folded values per group of consumer LDS reads
+  static constexpr int PD = 8;
+  static constexpr int PIN = 6;
+  // split schedule, stage 2: y lines in quarters over all NT threads (4 x 256 slots) instead
+  // of halves over the producers
+  static constexpr bool S2Q = false;
   static constexpr size_t w_elems = size_t(Z) * K * WS;
   static constexpr size_t w_bytes = w_elems * sizeof(cpx<T>);
   // stage 1's output buffer [Z][K][K] beside W (double buffering across terms)
@@ -354,12 +373,88 @@ __global__ __launch_bounds__(512) void k_forward_split(const T* __restrict__ f, 
 
 // ------------------------------------------------------------------------------------
 // kernel 2: one slab of one cell, all separable terms
+
+// After the last term of a slab: G, staged in LDS as [LINES][GS] reals at the start of the
+// buffer, goes through the forward x pass (real lines (z', y) -> k_x in [0, Kh] ->
+// W[z'][kx][y]; part h of a line takes the modes kx = XP j + h), the forward y pass and the
+// Z-point DFT over the slab planes, whose result is the slab's partial spectrum D[kx][ky][b]
+template <typename T, int N, int S>
+__device__ __forceinline__ void slab_forward(cpx<T>* W, cpx<T>* __restrict__ D) {
+  using C = Cfg<T, N, S>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, WS = C::WS, Z = C::Z;
+  constexpr int NT = C::NT, XP = C::XP, PX = P / XP;
+  const int tid = threadIdx.x;
+  T* Gst = reinterpret_cast<T*>(W);
+  cpx<T>* Wspec = reinterpret_cast<cpx<T>*>(reinterpret_cast<unsigned char*>(W) + C::gst_bytes);
+  __syncthreads();
+  if constexpr (!C::FWD_PARTS) {
+    // FP32: one thread per whole line (packed real transform)
+    for (int it = tid; it < C::LINES; it += NT) {
+      const int zp = it / P, y = it % P;
+      cpx<T> o[KH1];
+      rdft_low<P, KH1>(Gst + size_t(it) * C::GS, o);
+      static_for<0, KH1>([&](auto kx) { Wspec[(size_t(zp) * KH1 + kx) * WS + y] = o[kx]; });
+    }
+  } else if (tid < XP * C::LINES) {
+    const int h = tid / C::LINES, line = tid - h * C::LINES;
+    const int zp = line / P, y = line % P;
+    const T* gl = Gst + size_t(line) * C::GS;
+    cpx<T> u[PX];
+    part_dispatch<XP>(h, [&](auto hc) {
+      fold_part_fwd<P, XP, decltype(hc)::value>(u, [&](int i) { return cpx<T>{gl[i], T(0)}; });
+    });
+    dft<PX, -1>(u);
+    static_for<0, PX>([&](auto j) {
+      const int kx = XP * decltype(j)::value + h;
+      if (kx <= Kh) Wspec[(size_t(zp) * KH1 + kx) * WS + y] = u[j];
+    });
+  }
+  __syncthreads();
+  // forward y pass: lines (z', kx) -> ky in K, in place
+  if constexpr (!C::FWD_PARTS) {
+    for (int it = tid; it < Z * KH1; it += NT) {
+      cpx<T>* row = Wspec + size_t(it) * WS;
+      cpx<T> a[P];
+      static_for<0, P>([&](auto y) { a[y] = row[y]; });
+      dft<P, -1>(a);
+      static_for<0, K>([&](auto kyi) { row[kyi] = a[(decltype(kyi)::value - Kh + P) % P]; });
+    }
+  } else {
+    // in parts: every part reads its whole line before any part writes its modes back
+    constexpr int YL = Z * KH1;
+    static_assert(XP * YL <= NT, "one round of line parts");
+    const bool act = tid < XP * YL;
+    const int h = act ? tid / YL : 0, line = act ? tid - h * YL : 0;
+    cpx<T>* row = Wspec + size_t(line) * WS;
+    cpx<T> u[PX];
+    if (act) part_dispatch<XP>(h, [&](auto hc) { fold_part_fwd<P, XP, decltype(hc)::value>(u, [&](int i) { return row[i]; }); });
+    __syncthreads();
+    if (act) {
+      dft<PX, -1>(u);
+      static_for<0, PX>([&](auto j) {
+        const int k = XP * decltype(j)::value + h;   // DFT index of the output, signed mode k or k - P
+        if (k <= Kh) row[k + Kh] = u[j];
+        else if (k >= P - Kh) row[k - P + Kh] = u[j];
+      });
+    }
+  }
+  __syncthreads();
+  // Z-point forward DFT over the slab planes -> D[kx][ky][b]
+  for (int it = tid; it < KH1 * K; it += NT) {
+    const int kx = it / K, ky = it % K;
+    cpx<T> a[Z];
+    static_for<0, Z>([&](auto zp) { a[zp] = Wspec[(size_t(zp) * KH1 + kx) * WS + ky]; });
+    dft<Z, -1>(a);
+    static_for<0, Z>([&](auto b) { D[size_t(it) * Z + b] = a[b]; });
+  }
+}
+
 template <typename T, int N, int S, int RID>
 __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T* __restrict__ tab,
                                           int n_terms, int t_begin, int t_end, cpx<T>* __restrict__ D,
                                           cpx<T>* W) {
   using C = Cfg<T, N, S>;
-  constexpr int P = C::P, K = C::K, Kh = C::Kh, KH1 = C::KH1, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
   constexpr int NT = C::NT;
   const int tid = threadIdx.x;
 
@@ -549,76 +644,206 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
     }
   }
 
-  // forward x pass: real G lines (z', y) -> kx in [0, Kh] -> W[z'][kx][y]; the line
-  // parts are staged as whole lines, then part h of a line takes the modes kx = XP j + h
-  // (the same part split as the inverse passes: P/XP values per thread)
   T* Gst = reinterpret_cast<T*>(W);
-  cpx<T>* Wspec = reinterpret_cast<cpx<T>*>(reinterpret_cast<unsigned char*>(W) + C::gst_bytes);
   if (tid < XP * C::LINES) {
     const int h = tid / C::LINES, line = tid - h * C::LINES;
     static_for<0, PX>([&](auto j) { Gst[size_t(line) * C::GS + XP * decltype(j)::value + h] = g[j]; });
   }
-  __syncthreads();
-  if constexpr (!C::FWD_PARTS) {
-    // FP32: one thread per whole line (packed real transform)
-    for (int it = tid; it < C::LINES; it += NT) {
-      const int zp = it / P, y = it % P;
-      cpx<T> o[KH1];
-      rdft_low<P, KH1>(Gst + size_t(it) * C::GS, o);
-      static_for<0, KH1>([&](auto kx) { Wspec[(size_t(zp) * KH1 + kx) * WS + y] = o[kx]; });
+  slab_forward<T, N, S>(W, D);
+}
+
+// The same slab computation with the waves split into producers and consumers (C::SPLIT).
+// Producer waves keep their pencil's f̂ rows, already multiplied by the slab's chunk
+// twiddles, in registers for all terms, so a term's stage 1 reads only its table rows
+// (half of the L2 traffic of the plain schedule); they also run stage 2.  Consumer waves
+// run stage 3 for IPC x-line parts each and hold those parts of G.  Both sides pass the
+// same barriers: stage 1 of term t+1 (producers) and stage 3 of term t (consumers) share
+// one barrier interval, as in the plain schedule.
+template <typename T, int N, int S, int RID>
+__device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, const T* __restrict__ tab,
+                                                int n_terms, int t_begin, int t_end, cpx<T>* __restrict__ D,
+                                                cpx<T>* W) {
+  using C = Cfg<T, N, S>;
+  constexpr int P = C::P, K = C::K, Kh = C::Kh, WS = C::WS, Z = C::Z, NPAIR = C::NPAIR;
+  constexpr int XP = C::XP, PX = P / XP, PW = C::PW, CT = C::CT, IPC = C::IPC, LINES = C::LINES, XP3 = C::XP3;
+  static_assert(C::SPLIT, "split schedule only");
+  static_assert(XP * Z * K <= 64 * PW && NPAIR <= 64 * PW, "producers cover stage 1 and stage 2");
+  static_assert(IPC * CT == XP3 * LINES && CT % 64 == 0, "consumers cover stage 3");
+  cpx<T>* X = W + C::w_elems;
+  auto fold = [&](cpx<T>* u, int h, auto&& load) {
+    part_dispatch<XP>(h, [&](auto hc) { fold_part<P, XP, Kh, decltype(hc)::value>(u, load); });
+  };
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  // stage 2 in quarters: slot tid = 256 h + line, part h (outputs y = 4 j + h) of y line
+  // `line` < Z K; h is uniform over a wave
+  auto stage2q = [&] {
+    constexpr int HL = Z * K;
+    static_assert(HL <= 256 && C::NT == 1024 && P % 4 == 0, "quarter slots");
+    const int tid = opaque_tid();
+    const int h = __builtin_amdgcn_readfirstlane(tid >> 8), line = tid & 255;
+    if (line < HL) {
+      const cpx<T>* src = X + size_t(line) * K;
+      cpx<T>* row = W + size_t(line) * WS;
+      auto load = [&](int i) {
+        int z0 = 0;
+        asm volatile("" : "+v"(z0));
+        return src[i + z0];
+      };
+      auto pin = [](const cpx<T>& v, auto kk) {
+        if constexpr (decltype(kk)::value % C::PIN == C::PIN - 1) asm volatile("" ::"v"(v.re), "v"(v.im));
+      };
+      cpx<T> u[P / 4];
+      part_dispatch<4>(h, [&](auto hc) { fold_part<P, 4, Kh, decltype(hc)::value>(u, load, pin); });
+      dft<P / 4, +1>(u);
+      static_for<0, P / 4>([&](auto j) { row[4 * decltype(j)::value + h] = u[j]; });
     }
-  } else if (tid < XP * C::LINES) {
-    const int h = tid / C::LINES, line = tid - h * C::LINES;
-    const int zp = line / P, y = line % P;
-    const T* gl = Gst + size_t(line) * C::GS;
-    cpx<T> u[PX];
-    part_dispatch<XP>(h, [&](auto hc) {
-      fold_part_fwd<P, XP, decltype(hc)::value>(u, [&](int i) { return cpx<T>{gl[i], T(0)}; });
+  };
+  if (wave < PW) {
+    // ---- producers.  Rows r = 1 .. N-1 of the [row][pencil] layout (k_z = r - N/2; row 0,
+    // the dropped Nyquist mode, is zero); row r lies in chunk r / Z, bin r % Z.
+    constexpr uint32_t row_bytes = uint32_t(NPAIR) * sizeof(cpx<T>);
+    constexpr int NR = N - 1;
+    const __amdgpu_buffer_rsrc_t rf = make_rsrc(fh, uint32_t(C::NRL) * row_bytes);
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(tab, uint32_t(n_terms) * C::NRL * row_bytes);
+    const int p = opaque_tid();
+    const bool act = p < NPAIR;
+    // lanes past the last pencil read (and never use) the first pencils of the next row;
+    // reads past the end of a buffer return zero
+    const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+    cpx<T> gf[NR];
+    static_for<0, NR>([&](auto i) {
+      constexpr int r = decltype(i)::value + 1;
+      gf[i] = twiddle<S, +1, long(r / Z) * RID>(bload2<T>(rf, voff, uint32_t(r) * row_bytes));
     });
-    dft<PX, -1>(u);
-    static_for<0, PX>([&](auto j) {
-      const int kx = XP * decltype(j)::value + h;
-      if (kx <= Kh) Wspec[(size_t(zp) * KH1 + kx) * WS + y] = u[j];
-    });
-  }
-  __syncthreads();
-  // forward y pass: lines (z', kx) -> ky in K, in place
-  if constexpr (!C::FWD_PARTS) {
-    for (int it = tid; it < Z * KH1; it += NT) {
-      cpx<T>* row = Wspec + size_t(it) * WS;
-      cpx<T> a[P];
-      static_for<0, P>([&](auto y) { a[y] = row[y]; });
-      dft<P, -1>(a);
-      static_for<0, K>([&](auto kyi) { row[kyi] = a[(decltype(kyi)::value - Kh + P) % P]; });
+    constexpr int PD = C::PD < NR ? C::PD : NR;
+    auto stage1 = [&](int t) {
+      const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
+      cpx<T> ta[PD];
+      static_for<0, PD>([&](auto i) { ta[i] = bload2<T>(rt, voff, tterm + uint32_t(decltype(i)::value + 1) * row_bytes); });
+      // (a + ib) g and its mirror conj((a - ib) g) from s1 = sum a Re g, s2 = sum b Im g,
+      // s3 = sum a Im g, s4 = sum b Re g per bin
+      T s1[Z], s2[Z], s3[Z], s4[Z];
+      static_for<0, Z>([&](auto bb) {
+        s1[bb] = T(0);
+        s2[bb] = T(0);
+        s3[bb] = T(0);
+        s4[bb] = T(0);
+      });
+      static_for<0, NR>([&](auto i) {
+        constexpr int ii = decltype(i)::value, r = ii + 1, bb = r % Z, slot = ii % PD;
+        sched_fence();
+        const cpx<T> ab = ta[slot];
+        const cpx<T> g = gf[ii];
+        s1[bb] += ab.re * g.re;
+        s2[bb] += ab.im * g.im;
+        s3[bb] += ab.re * g.im;
+        s4[bb] += ab.im * g.re;
+        // the sums of this row are formed before the next load is issued
+        asm volatile("" ::"v"(s1[bb]), "v"(s2[bb]), "v"(s3[bb]), "v"(s4[bb]));
+        if constexpr (ii + PD < NR) {
+          // an opaque copy of the offset keeps the load in its place in the ring (the
+          // loads of read-only memory are otherwise all hoisted to the top)
+          uint32_t vo = voff;
+          asm volatile("" : "+v"(vo));
+          ta[slot] = bload2<T>(rt, vo, tterm + uint32_t(r + PD) * row_bytes);
+        }
+      });
+      int kx, ky;
+      pair_kxy<K, Kh>(act ? p : 0, kx, ky);
+      cpx<T> oA[Z], oB[Z];
+      static_for<0, Z>([&](auto bb) {
+        constexpr int e = decltype(bb)::value - N / 2;
+        const cpx<T> bA = {s1[bb] - s2[bb], s3[bb] + s4[bb]};
+        const cpx<T> bB = {s1[bb] + s2[bb], s4[bb] - s3[bb]};
+        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA);
+        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB);
+      });
+      if (act) {
+        dft<Z, +1>(oA);
+        const int kxa = kx + Kh, kya = ky + Kh;
+        static_for<0, Z>([&](auto zp) { X[(size_t(zp) * K + kxa) * K + kya] = oA[zp]; });
+        if (kx != 0 || ky != 0) {
+          dft<Z, +1>(oB);
+          const int kxb = Kh - kx, kyb = Kh - ky;
+          static_for<0, Z>([&](auto zp) { X[(size_t(zp) * K + kxb) * K + kyb] = oB[zp]; });
+        }
+      }
+    };
+    if (t_begin < t_end) stage1(t_begin);
+    __syncthreads();
+    for (int t = t_begin; t < t_end; ++t) {
+      if constexpr (C::S2Q) {
+        stage2q();
+      } else {
+        // stage 2: y lines (z', kx) of X -> W, part h of line `line`
+        const int tid = opaque_tid();
+        constexpr int HL = Z * K;
+        if (tid < XP * HL) {
+          const int h = tid / HL, line = tid - h * HL;
+          const cpx<T>* src = X + size_t(line) * K;
+          cpx<T>* row = W + size_t(line) * WS;
+          cpx<T> u[PX];
+          fold(u, h, [&](int i) { return src[i]; });
+          dft<PX, +1>(u);
+          static_for<0, PX>([&](auto j) { row[XP * decltype(j)::value + h] = u[j]; });
+        }
+      }
+      __syncthreads();
+      if (t + 1 < t_end) stage1(t + 1);
+      __syncthreads();
     }
   } else {
-    // in parts: every part reads its whole line before any part writes its modes back
-    constexpr int YL = Z * KH1;
-    static_assert(XP * YL <= NT, "one round of line parts");
-    const bool act = tid < XP * YL;
-    const int h = act ? tid / YL : 0, line = act ? tid - h * YL : 0;
-    cpx<T>* row = Wspec + size_t(line) * WS;
-    cpx<T> u[PX];
-    if (act) part_dispatch<XP>(h, [&](auto hc) { fold_part_fwd<P, XP, decltype(hc)::value>(u, [&](int i) { return row[i]; }); });
+    // ---- consumers: x-line part it = c + m CT (m < IPC) of stage 3, i.e. part h = it / LINES
+    // (outputs y = XP3 j + h) of line it % LINES; G part g[m]
+    constexpr int PX3 = P / XP3;
+    T g[IPC][PX3];
+    static_for<0, IPC>([&](auto m) { static_for<0, PX3>([&](auto j) { g[m][j] = T(0); }); });
     __syncthreads();
-    if (act) {
-      dft<PX, -1>(u);
-      static_for<0, PX>([&](auto j) {
-        const int k = XP * decltype(j)::value + h;   // DFT index of the output, signed mode k or k - P
-        if (k <= Kh) row[k + Kh] = u[j];
-        else if (k >= P - Kh) row[k - P + Kh] = u[j];
+    for (int t = t_begin; t < t_end; ++t) {
+      if constexpr (C::S2Q) stage2q();
+      __syncthreads();
+      const int c = opaque_tid() - 64 * PW;
+      static_for<0, IPC>([&](auto m) {
+        sched_fence();
+        constexpr int mm = decltype(m)::value;
+        const int it = c + mm * CT;
+        // the CT parts of round mm span the part indices hlo .. hhi (at most two); h is
+        // uniform over a wave
+        constexpr int hlo = mm * CT / LINES, hhi = (mm * CT + CT - 1) / LINES;
+        static_assert(hhi - hlo <= 1, "a round spans at most two part indices");
+        const int h = hlo == hhi ? hlo : __builtin_amdgcn_readfirstlane(it / LINES);
+        const int line = it - h * LINES;
+        const int zp = line / P, y = line % P;
+        const cpx<T>* col = W + size_t(zp) * K * WS + y;
+        // each LDS read takes an opaque zero offset and every C::PIN-th folded value is formed
+        // before the next read is issued: the reads of a part are not all hoisted to its top
+        // (its 31 inputs, the part and G together exceed the registers)
+        auto load = [&](int i) {
+          int z0 = 0;
+          asm volatile("" : "+v"(z0));
+          return col[size_t(i) * WS + z0];
+        };
+        auto pin = [](const cpx<T>& v, auto kk) {
+          if constexpr (decltype(kk)::value % C::PIN == C::PIN - 1) asm volatile("" ::"v"(v.re), "v"(v.im));
+        };
+        cpx<T> u[PX3];
+        if (hlo == hhi || h == hlo) fold_part<P, XP3, Kh, hlo>(u, load, pin);
+        else fold_part<P, XP3, Kh, hhi>(u, load, pin);
+        dft<PX3, +1>(u);
+        static_for<0, PX3>([&](auto j) { g[m][j] += u[j].re * u[j].im; });
       });
+      __syncthreads();
     }
+    // stage G for the forward passes (after the last barrier no part reads W)
+    T* Gst = reinterpret_cast<T*>(W);
+    const int c = int(threadIdx.x) - 64 * PW;
+    static_for<0, IPC>([&](auto m) {
+      const int it = c + decltype(m)::value * CT;
+      const int h = it / LINES, line = it - h * LINES;
+      static_for<0, PX3>([&](auto j) { Gst[size_t(line) * C::GS + XP3 * decltype(j)::value + h] = g[m][j]; });
+    });
   }
-  __syncthreads();
-  // Z-point forward DFT over the slab planes -> D[kx][ky][b]
-  for (int it = tid; it < KH1 * K; it += NT) {
-    const int kx = it / K, ky = it % K;
-    cpx<T> a[Z];
-    static_for<0, Z>([&](auto zp) { a[zp] = Wspec[(size_t(zp) * KH1 + kx) * WS + ky]; });
-    dft<Z, -1>(a);
-    static_for<0, Z>([&](auto b) { D[size_t(it) * Z + b] = a[b]; });
-  }
+  slab_forward<T, N, S>(W, D);
 }
 
 template <typename T, int N, int S>
@@ -648,7 +873,10 @@ __global__ __launch_bounds__((Cfg<T, N, S>::NT)) void k_slab(const cpx<T>* __res
   const cpx<T>* fh = fhat + size_t(cell) * C::NRL * C::NPAIR;
   cpx<T>* Ds = D + (size_t(unit) * C::S + r) * (size_t(C::KH1) * C::K * C::Z);
   static_for<0, C::S>([&](auto rid) {
-    if (r == decltype(rid)::value) slab_body<T, N, S, decltype(rid)::value>(fh, tab, n_terms, t0, t1, Ds, W);
+    if (r == decltype(rid)::value) {
+      if constexpr (C::SPLIT) slab_body_split<T, N, S, decltype(rid)::value>(fh, tab, n_terms, t0, t1, Ds, W);
+      else slab_body<T, N, S, decltype(rid)::value>(fh, tab, n_terms, t0, t1, Ds, W);
+    }
   });
 }
 

@@ -245,8 +245,8 @@ __device__ __forceinline__ void fold_half(cpx<T>* u, Load&& load) {
 // n/R-point inverse DFT of u[k'] = w^{k' h} sum_{q < R} c[k' + q n/R] exp(2 pi i q h / R).
 // R = 2 is fold_half.  More parts hold fewer values per thread (n/R) at the price of
 // every part reading all nonzero inputs.
-template <int n, int R, int kh, int h, typename T, class Load>
-__device__ __forceinline__ void fold_part(cpx<T>* u, Load&& load) {
+template <int n, int R, int kh, int h, typename T, class Load, class Pin>
+__device__ __forceinline__ void fold_part(cpx<T>* u, Load&& load, Pin&& pin) {
   static_assert(n % R == 0, "parts must divide the length");
   constexpr int m = n / R;
   static_for<0, m>([&](auto kk) {
@@ -264,8 +264,13 @@ __device__ __forceinline__ void fold_part(cpx<T>* u, Load&& load) {
       }
     });
     u[kp] = twiddle<n, +1, long(kp) * h>(v);
+    pin(u[kp], kk);
     if constexpr (kp % 6 == 5) sched_fence();
   });
+}
+template <int n, int R, int kh, int h, typename T, class Load>
+__device__ __forceinline__ void fold_part(cpx<T>* u, Load&& load) {
+  fold_part<n, R, kh, h>(u, load, [](const cpx<T>&, auto) {});
 }
 
 // Forward (sign -1) counterpart with every input present: outputs Y[R j + h], j < n/R, of
