@@ -107,7 +107,8 @@ struct Cfg : Grid<T, N> {
   static constexpr int NT = SPLIT ? 64 * PW + CT : NT_PLAIN;
   // table rows in flight per producer thread; folded values per group of consumer LDS reads
   static constexpr int PD = 8;
-  static constexpr int PIN = 6;
+  static constexpr int PIN = 3;
+  static constexpr int VG = 1;
   // split schedule, stage 2: y lines in quarters over all NT threads (4 x 256 slots) instead
   // of halves over the producers
   static constexpr bool S2Q = false;
@@ -720,6 +721,7 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
       const uint32_t tterm = uint32_t(t) * C::NRL * row_bytes;
       cpx<T> ta[PD];
       static_for<0, PD>([&](auto i) { ta[i] = bload2<T>(rt, voff, tterm + uint32_t(decltype(i)::value + 1) * row_bytes); });
+      uint32_t vo = voff;
       // (a + ib) g and its mirror conj((a - ib) g) from s1 = sum a Re g, s2 = sum b Im g,
       // s3 = sum a Im g, s4 = sum b Re g per bin
       T s1[Z], s2[Z], s3[Z], s4[Z];
@@ -738,15 +740,15 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
         s2[bb] += ab.im * g.im;
         s3[bb] += ab.re * g.im;
         s4[bb] += ab.im * g.re;
-        // the sums of this row are formed before the next load is issued
-        asm volatile("" ::"v"(s1[bb]), "v"(s2[bb]), "v"(s3[bb]), "v"(s4[bb]));
-        if constexpr (ii + PD < NR) {
-          // an opaque copy of the offset keeps the load in its place in the ring (the
-          // loads of read-only memory are otherwise all hoisted to the top)
-          uint32_t vo = voff;
-          asm volatile("" : "+v"(vo));
-          ta[slot] = bload2<T>(rt, vo, tterm + uint32_t(r + PD) * row_bytes);
+        // the sums of this row are formed before the next load is issued; the loads take an
+        // opaque copy of the offset, renewed every C::VG rows, which keeps them in their
+        // place in the ring (the loads of read-only memory are otherwise all hoisted to the top)
+        if constexpr (ii % C::VG == 0) {
+          asm volatile("" : "+v"(vo) : "v"(s1[bb]), "v"(s2[bb]), "v"(s3[bb]), "v"(s4[bb]));
+        } else {
+          asm volatile("" ::"v"(s1[bb]), "v"(s2[bb]), "v"(s3[bb]), "v"(s4[bb]));
         }
+        if constexpr (ii + PD < NR) ta[slot] = bload2<T>(rt, vo, tterm + uint32_t(r + PD) * row_bytes);
       });
       int kx, ky;
       pair_kxy<K, Kh>(act ? p : 0, kx, ky);
@@ -815,16 +817,14 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
         const int line = it - h * LINES;
         const int zp = line / P, y = line % P;
         const cpx<T>* col = W + size_t(zp) * K * WS + y;
-        // each LDS read takes an opaque zero offset and every C::PIN-th folded value is formed
-        // before the next read is issued: the reads of a part are not all hoisted to its top
+        // the LDS reads take an opaque zero offset that is renewed after every C::PIN-th folded
+        // value, once that value is formed: the reads of a part are not all hoisted to its top
         // (its 31 inputs, the part and G together exceed the registers)
-        auto load = [&](int i) {
-          int z0 = 0;
-          asm volatile("" : "+v"(z0));
-          return col[size_t(i) * WS + z0];
-        };
-        auto pin = [](const cpx<T>& v, auto kk) {
-          if constexpr (decltype(kk)::value % C::PIN == C::PIN - 1) asm volatile("" ::"v"(v.re), "v"(v.im));
+        int z0 = 0;
+        asm volatile("" : "+v"(z0));
+        auto load = [&](int i) { return col[size_t(i) * WS + z0]; };
+        auto pin = [&z0](const cpx<T>& v, auto kk) {
+          if constexpr (decltype(kk)::value % C::PIN == C::PIN - 1) asm volatile("" : "+v"(z0) : "v"(v.re), "v"(v.im));
         };
         cpx<T> u[PX3];
         if (hlo == hhi || h == hlo) fold_part<P, XP3, Kh, hlo>(u, load, pin);
