@@ -112,6 +112,10 @@ struct Cfg : Grid<T, N> {
   // split schedule, stage 2: y lines in quarters over all NT threads (4 x 256 slots) instead
   // of halves over the producers
   static constexpr bool S2Q = false;
+  // plain schedule, FP64: f̂ rows 1 .. RES of the thread's pencil stay in registers for all
+  // terms (chunk-twiddled), so stage 1 loads only their table rows; row 0 (the dropped
+  // Nyquist mode) is neither loaded nor accumulated
+  static constexpr int RES = (sizeof(T) == 8 && N == 32) ? 16 : 0;
   static constexpr size_t w_elems = size_t(Z) * K * WS;
   static constexpr size_t w_bytes = w_elems * sizeof(cpx<T>);
   // stage 1's output buffer [Z][K][K] beside W (double buffering across terms)
@@ -492,13 +496,25 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
   struct Pipe {
     cpx<T> pf[DEPTH][ZH], pa[DEPTH][ZH];
   };
+  // f̂ rows 1 .. RES in registers (C::RES > 0), each times its chunk twiddle w_S^{jr}
+  constexpr int RES = C::RES;
+  cpx<T> gres[RES > 0 ? RES : 1];
+  if constexpr (RES > 0) {
+    const uint32_t voff = uint32_t(opaque_tid()) * sizeof(cpx<T>);
+    static_for<0, RES>([&](auto i) {
+      constexpr int r = decltype(i)::value + 1;
+      gres[i] = twiddle<C::S, +1, long(r / Z) * RID>(bload2<T>(rf, voff, uint32_t(r) * row_bytes));
+    });
+  }
+  // rows 0 .. row_live_from - 1 take no f̂ load (zero, or held in gres)
   auto load_half = [&](Pipe& q, uint32_t voff, uint32_t tterm, auto hc) {
     constexpr int h = decltype(hc)::value, slot = h % DEPTH, b0 = (h % 2) * ZH;
     constexpr uint32_t s0 = uint32_t(h / 2) * Z * row_bytes;
     static_for<0, ZH>([&](auto i) {
       constexpr int bb = b0 + decltype(i)::value;
-      if constexpr (bb < Z) {
-        q.pf[slot][i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
+      constexpr int row = (h / 2) * Z + bb;
+      if constexpr (bb < Z && !(RES > 0 && row == 0)) {
+        if constexpr (!(RES > 0 && row <= RES)) q.pf[slot][i] = bload2<T>(rf, voff, s0 + uint32_t(bb) * row_bytes);
         q.pa[slot][i] = bload2<T>(rt, voff, tterm + s0 + uint32_t(bb) * row_bytes);
       }
     });
@@ -530,9 +546,12 @@ __device__ __forceinline__ void slab_body(const cpx<T>* __restrict__ fh, const T
       constexpr long qe = long(h / 2) * RID;
       static_for<0, ZH>([&](auto i) {
         constexpr int bb = b0 + decltype(i)::value;
-        if constexpr (bb < Z) {
+        constexpr int row = (h / 2) * Z + bb;
+        if constexpr (bb < Z && !(RES > 0 && row == 0)) {
           const cpx<T> ab = q.pa[slot][i];
-          const cpx<T> g = twiddle<C::S, +1, qe>(q.pf[slot][i]);
+          cpx<T> g;
+          if constexpr (RES > 0 && row <= RES) g = gres[row - 1];
+          else g = twiddle<C::S, +1, qe>(q.pf[slot][i]);
           if constexpr (sizeof(T) == 8) {
             // FP64: sums in program order.  Reassociated, the unrolled chunk products
             // are regrouped by twiddle constant and all kept live (hundreds of spilled
