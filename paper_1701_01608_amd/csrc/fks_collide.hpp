@@ -730,10 +730,13 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
     // lanes past the last pencil read (and never use) the first pencils of the next row;
     // reads past the end of a buffer return zero
     const uint32_t voff = uint32_t(p) * sizeof(cpx<T>);
+    // row r carries the whole slab twiddle exp(2 pi i k_z r_slab / P), k_z = r - N/2: the
+    // chunk factor and the per-bin factor of the plain schedule in one (the bin sums then
+    // need no twiddle)
     cpx<T> gf[NR];
     static_for<0, NR>([&](auto i) {
       constexpr int r = decltype(i)::value + 1;
-      gf[i] = twiddle<S, +1, long(r / Z) * RID>(bload2<T>(rf, voff, uint32_t(r) * row_bytes));
+      gf[i] = twiddle<P, +1, long(r - N / 2) * RID>(bload2<T>(rf, voff, uint32_t(r) * row_bytes));
     });
     constexpr int PD = C::PD < NR ? C::PD : NR;
     auto stage1 = [&](int t) {
@@ -774,10 +777,8 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
       cpx<T> oA[Z], oB[Z];
       static_for<0, Z>([&](auto bb) {
         constexpr int e = decltype(bb)::value - N / 2;
-        const cpx<T> bA = {s1[bb] - s2[bb], s3[bb] + s4[bb]};
-        const cpx<T> bB = {s1[bb] + s2[bb], s4[bb] - s3[bb]};
-        oA[((e % Z) + Z) % Z] = twiddle<P, +1, long(e) * RID>(bA);
-        oB[(((-e) % Z) + Z) % Z] = twiddle<P, +1, -long(e) * RID>(bB);
+        oA[((e % Z) + Z) % Z] = cpx<T>{s1[bb] - s2[bb], s3[bb] + s4[bb]};
+        oB[(((-e) % Z) + Z) % Z] = cpx<T>{s1[bb] + s2[bb], s4[bb] - s3[bb]};
       });
       if (act) {
         dft<Z, +1>(oA);
