@@ -100,7 +100,8 @@ struct Cfg : Grid<T, N> {
   // 64), and the workgroup stays within 1024 threads.
   static constexpr int PW = ((NPAIR + 63) / 64 > (XP * Z * K + 63) / 64) ? (NPAIR + 63) / 64 : (XP * Z * K + 63) / 64;
   static constexpr int XP3 = 4;
-  static constexpr int CT = 512;
+  // the fewest consumer threads (a multiple of 64) that take the parts in shares of three
+  static constexpr int CT = (XP3 * LINES + 3 * 64 - 1) / (3 * 64) * 64;
   static constexpr bool SPLIT = sizeof(T) == 4 && 64 * PW + CT <= 1024 && P % XP3 == 0 &&
                                 (XP3 * LINES) % CT == 0 && (XP3 * LINES) / CT <= 3 && LINES % 64 == 0;
   static constexpr int IPC = SPLIT ? XP3 * LINES / CT : 0;
@@ -698,7 +699,7 @@ __device__ __forceinline__ void slab_body_split(const cpx<T>* __restrict__ fh, c
   // `line` < Z K; h is uniform over a wave
   auto stage2q = [&] {
     constexpr int HL = Z * K;
-    static_assert(HL <= 256 && C::NT == 1024 && P % 4 == 0, "quarter slots");
+    static_assert(!C::S2Q || (HL <= 256 && C::NT == 1024 && P % 4 == 0), "quarter slots");
     const int tid = opaque_tid();
     const int h = __builtin_amdgcn_readfirstlane(tid >> 8), line = tid & 255;
     if (line < HL) {
