@@ -38,7 +38,7 @@ CPU_SHARE = 16                    # host cores one single-GPU job is given
 # HBM bytes per k_slab<float,32> launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hbm_traffic_*.md); valid only
 # for the kernel sources with this hash, otherwise the traffic field is reported as null.
-SLAB_TRAFFIC = {"sha": "9102949f0da4d3fc", "bytes": 1851688320}
+SLAB_TRAFFIC = {"sha": "7d46bdb22bd61038", "bytes": 2032597888}
 
 
 def progress(msg):
