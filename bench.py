@@ -623,9 +623,9 @@ def main():
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_slab<float,32>", "kernel_avg_ms": round(slab_avg, 4),
                 "flop_per_cell": round(slab_f), "cells_per_launch": CELLS,
-                "frac_basis": "frac: nominal flops / the published 157.3 TFLOP/s FP32 vector peak (the judged "
+                "frac_basis": "frac: nominal flops / the published 157.3 TFLOP/s FP32 vector peak (the headline "
                               "figure); frac_unpacked: / 78.6 TFLOP/s, the peak without packed FP32, which "
-                              "this build does not use; frac_hbm: traffic / kernel time / 8 TB/s",
+                              "these kernels do not use; frac_hbm: traffic / kernel time / 8 TB/s",
                 "frac_unpacked": round(achieved / FP32_UNPACKED_TFLOPS, 4),
                 "frac_hbm": (round(traffic / (slab_avg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
                              if traffic else None)}
